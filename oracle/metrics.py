@@ -1,0 +1,37 @@
+"""Error measures used to compare a result with the oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rel_l2(x, ref) -> float:
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    n = np.linalg.norm(ref.ravel())
+    return float(np.linalg.norm((x - ref).ravel()) / (n if n > 0 else 1.0))
+
+
+def max_rel(x, ref) -> float:
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    m = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / (m if m > 0 else 1.0))
+
+
+def psnr_maxnorm(img, ref_img) -> float:
+    a = np.asarray(img, dtype=np.float64)
+    b = np.asarray(ref_img, dtype=np.float64)
+    a = a / (a.max() if a.max() > 0 else 1.0)
+    b = b / (b.max() if b.max() > 0 else 1.0)
+    mse = np.mean((a - b) ** 2)
+    return float("inf") if mse == 0 else float(10.0 * np.log10(1.0 / mse))
+
+
+def argmax_index(v):
+    return np.unravel_index(int(np.argmax(v)), np.shape(v))
+
+
+def argmax_distance(x, ref) -> float:
+    a = np.array(argmax_index(x), dtype=np.float64)
+    b = np.array(argmax_index(ref), dtype=np.float64)
+    return float(np.abs(a - b).max())
