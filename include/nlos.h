@@ -1,0 +1,199 @@
+/*
+ * nlos.h -- C ABI of the MI355X NLOS reconstruction library (libnlos.so).
+ *
+ * Three operations of wave-based non-line-of-sight reconstruction, after
+ * López-Ruiz & Royo, "Memory-efficient GPU pipelines for real-time
+ * non-line-of-sight reconstruction":
+ *   nlos_bin  -- photon events -> transient histogram (Section 4.1, photon binner)
+ *   nlos_fk   -- f-k migration of a confocal transient (Section 3.1 Eq. 1-2,
+ *                Section 4.2, Algorithms 1-2 of the supplementary material)
+ *   nlos_rsd  -- phasor-field RSD with the radial kernel (Section 4.3 Eq. 4-7,
+ *                supplementary sampling rules, Listing 3, Algorithm 4)
+ *
+ * Conventions shared by every entry point
+ *   - Only plain C types cross this interface.  Pointers named d_* are device
+ *     (HBM) pointers on the context's device; every other pointer is host memory.
+ *   - The caller owns every buffer it passes (inputs, outputs, workspace) and
+ *     keeps it alive until the stream work completes.  Plans own their device
+ *     tables; a context owns its workspace pool and its twiddle table.
+ *   - Every call returns an nlos_status and never throws.  Arguments are
+ *     validated on the host before anything is enqueued; on an error nothing is
+ *     enqueued and nlos_last_error() describes the failure.
+ *   - Compute calls are asynchronous: they enqueue kernels on the context's HIP
+ *     stream and return.  A context is not thread safe; use one per host thread.
+ *   - Volumes are row-major with the last index contiguous.  A transient is
+ *     tau[ny][nx][nt] (time contiguous, scan point y*nx + x).  Complex values are
+ *     interleaved (re, im).  Results are deterministic: the same inputs give
+ *     bitwise-equal outputs, also when other work runs concurrently.
+ */
+#ifndef NLOS_H
+#define NLOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NLOS_OK = 0,
+  NLOS_ERR_INVALID_ARG = 1,   /* null pointer, non-positive size, bad enum, value out of range */
+  NLOS_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  NLOS_ERR_OUT_OF_MEMORY = 3, /* device allocation failed, or workspace too small */
+  NLOS_ERR_DEVICE = 4,        /* HIP runtime or launch failure */
+  NLOS_ERR_INTERNAL = 5
+} nlos_status;
+
+typedef enum { NLOS_FP32 = 0, NLOS_FP16 = 1, NLOS_BF16 = 2 } nlos_precision;
+
+typedef struct nlos_ctx nlos_ctx;
+typedef struct nlos_fk_plan nlos_fk_plan;
+typedef struct nlos_rsd_plan nlos_rsd_plan;
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Binds HIP device `device` and stream `hip_stream` (a hipStream_t; NULL means
+ * the null stream), uploads the FP64-generated twiddle table.  *out is set on
+ * NLOS_OK only.  NLOS_ERR_DEVICE if the device cannot be used. */
+nlos_status nlos_create(int device, void *hip_stream, nlos_ctx **out);
+/* Frees the context's pool and tables (waits for its stream first).  NULL is a no-op. */
+nlos_status nlos_destroy(nlos_ctx *ctx);
+/* Later calls on ctx enqueue on hip_stream. */
+nlos_status nlos_set_stream(nlos_ctx *ctx, void *hip_stream);
+/* Static text for a status code. */
+const char *nlos_status_string(nlos_status s);
+/* Detail of the last failure on ctx ("" if none); valid until the next call on ctx. */
+const char *nlos_last_error(const nlos_ctx *ctx);
+/* Library ABI version (major * 100 + minor). */
+int nlos_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Photon-event binning (Section 4.1: GPU histogramming of photon records)   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t pixel;   /* scan point y*nx + x */
+  uint32_t t_ps;   /* arrival time, picoseconds from the laser hitting the wall point */
+} nlos_event;
+
+typedef struct {
+  int nx, ny, nt;     /* histogram shape [ny][nx][nt], each >= 1 */
+  uint32_t bin_ps;    /* bin width, >= 1 */
+  uint32_t t0_ps;     /* time of the left edge of bin 0 */
+  int accumulate;     /* 0: d_hist is overwritten; 1: counts are added to it */
+} nlos_bin_desc;
+
+/* Host-only validation of a binning descriptor. */
+nlos_status nlos_bin_check(const nlos_bin_desc *desc);
+
+/* Histogram n_events events (AoS, 8 bytes each) into d_hist[ny][nx][nt] (uint32,
+ * time contiguous).  An event is valid iff 0 <= pixel < nx*ny, t_ps >= t0_ps and
+ * b = (t_ps - t0_ps) / bin_ps < nt (integer division, left-closed bins); it adds 1
+ * to d_hist[pixel][b].  Invalid events add 1 to *d_dropped (a device uint64,
+ * optional: NULL skips the count; it is zeroed first unless accumulate = 1).
+ * n_events may be 0.  Counts wrap modulo 2^32 per bin.  Bit-exact and order
+ * independent. */
+nlos_status nlos_bin(nlos_ctx *ctx, const nlos_bin_desc *desc, const nlos_event *d_events,
+                     uint64_t n_events, uint32_t *d_hist, unsigned long long *d_dropped);
+
+/* ------------------------------------------------------------------------ */
+/* f-k migration (Section 4.2; Algorithms 1-2)                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int nx, ny, nt;          /* transient shape [ny][nx][nt] */
+  double wall_w_m;         /* scanned wall extent along x (m); dx = wall_w_m / nx */
+  double wall_h_m;         /* along y (m); dy = wall_h_m / ny */
+  double bin_ps;           /* time-bin width (ps) */
+  int pad;                 /* 1 (no padding) or 2 (x2 zero padding on every axis) */
+  nlos_precision prec;     /* storage of the complex intermediates */
+} nlos_fk_desc;
+
+/* Host-only validation: dims >= 1, nt >= 2, pad in {1, 2}, pad*nx, pad*ny and
+ * pad*nt powers of two in [8, 2048] (else NLOS_ERR_UNSUPPORTED), positive
+ * finite geometry. */
+nlos_status nlos_fk_check(const nlos_fk_desc *desc);
+/* Exact device workspace one nlos_fk call needs (host only). */
+nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc *desc, size_t *bytes);
+nlos_status nlos_fk_plan_create(nlos_ctx *ctx, const nlos_fk_desc *desc, nlos_fk_plan **out);
+nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
+
+/* f-k migration of d_tau[ny][nx][nt] (float32 counts):
+ *   g = tau * t/(nt-1), zero-padded to My x Mx x Mt (M = pad * n);
+ *   unnormalised 3D DFT; Stolt remap out = [Z>0] (Z/Z') lerp_w(S, Z') with
+ *   Z' = sqrt(sx^2 X^2 + sy^2 Y^2 + Z^2), sx = c dt / (2 dx), sy = c dt / (2 dy),
+ *   X, Y, Z the signed frequencies normalised to [-1, 1), zero beyond the last
+ *   frequency sample; inverse 3D DFT normalised by 1/(Mx My Mt).
+ * Writes d_vol[ny][nx][nt] = |Psi|^2 on the unpadded grid and d_img[ny][nx] =
+ * max over depth of d_vol; either output may be NULL (not both).  d_ws is
+ * device workspace of ws_bytes >= nlos_fk_workspace_bytes (NULL: the context
+ * pool is used and grown as needed).  Inputs are not modified. */
+nlos_status nlos_fk(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_vol,
+                    float *d_img, void *d_ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Phasor-field RSD with the radial kernel (Section 4.3; Algorithm 4)        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int nx, ny, nt;          /* transient shape [ny][nx][nt] */
+  double dx_m, dy_m;       /* wall sample spacing (m) */
+  double bin_ps;           /* time-bin width (ps) */
+  int pad;                 /* 1 or 2: the 2D FFT grid is My x Mx = pad*ny x pad*nx */
+  int n_freq;              /* number of temporal frequencies, >= 1 */
+  const int32_t *freq_bin; /* host [n_freq]: DFT bins of nt, each in [1, nt/2 - 1] */
+  const float *w;          /* host [2*n_freq]: complex frequency weights (re, im) */
+  int n_depth;             /* number of depth planes, in [1, 4096] */
+  double depth0_m;         /* depth of plane 0 (m) */
+  double depth_step_m;     /* spacing of the depth planes (m) */
+  int sigma_s, sigma_t;    /* modality: (2, 0) confocal, (1, 1) non-confocal */
+  double delta_m;          /* calibration offset of the optical path (m) */
+  nlos_precision data_prec;   /* storage of the complex intermediates */
+  nlos_precision kernel_prec; /* storage of the radial kernel K_r */
+} nlos_rsd_desc;
+
+/* Radial sampling of the supplementary material: r_max, rho_max, ring count
+ * N_r (power of two >= ceil(2 sigma_s r_max / lambda_min) + 1, at least 2),
+ * radius count N_rho (power of two >= ceil(2 r_max rho_max) + 1), ring spacing,
+ * sampling rate f_s = (N_r - 1)/r_max, cutoff min(rho_max, f_s/2) and its bin
+ * coordinate, and the clamped lookup bounds of Listing 3. */
+typedef struct {
+  double r_max, rho_max, lambda_min, dr, f_s, rho_cut, rho_cut_bin;
+  int n_r_min, n_r, n_rho_min, n_rho, cut_idx, last_base;
+} nlos_rsd_geometry;
+
+/* Host-only validation: dims >= 1, pad in {1, 2}, pad*nx, pad*ny and nt powers
+ * of two in [8, 2048] (else NLOS_ERR_UNSUPPORTED), frequency bins in range,
+ * positive spacings, n_depth in [1, 4096], sigma_s in {1, 2}. */
+nlos_status nlos_rsd_check(const nlos_rsd_desc *desc);
+/* Host-only: the radial sampling geometry of desc. */
+nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc *desc, nlos_rsd_geometry *out);
+/* Host-only: builds the radial kernel of Eq. 6 in FP64 exactly as a plan does and
+ * stores it as float (re, im) into out[n_rho][n_freq][n_depth][2]; n_floats must
+ * be at least 2 * n_rho * n_freq * n_depth. */
+nlos_status nlos_rsd_kernel_host(const nlos_rsd_desc *desc, float *out, size_t n_floats);
+/* Exact device workspace one nlos_rsd call needs (host only). */
+nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc *desc, size_t *bytes);
+/* Builds K_r (Eq. 4-6, FP64 on the host, stored per kernel_prec), the pixel-to-
+ * radius map and the frequency tables, and uploads them to HBM. */
+nlos_status nlos_rsd_plan_create(nlos_ctx *ctx, const nlos_rsd_desc *desc, nlos_rsd_plan **out);
+nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan *plan);
+
+/* Radial RSD of d_tau[ny][nx][nt] (float32):
+ *   P[f] = sum_t tau e^{-2 pi i k_f t / nt};  P^ = DFT2(P padded top-left);
+ *   C[d](u,v) = sum_f w_f P^[f](u,v) a(rho) lerp(K_r[., f, d], rho(u,v)) with the
+ *   smoothstep taper a over the last 8 radial bins below the cutoff;
+ *   I[d] = IDFT2(C[d]) normalised by 1/(Mx My).
+ * Writes d_vol[n_depth][ny][nx] = |I| on the unpadded grid and d_img[ny][nx] =
+ * max over depth; either may be NULL (not both).  Workspace as for nlos_fk. */
+nlos_status nlos_rsd(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
+                     float *d_img, void *d_ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLOS_H */

@@ -1,0 +1,77 @@
+// Photon-event binning and small utility kernels (gfx950, wave64).
+#include "nlos_internal.hpp"
+
+namespace nlos {
+
+__global__ __launch_bounds__(256) void fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
+// One event per lane, grid-stride over wave-sized chunks so that every lane of a
+// wave takes the same trip count.  Lanes that target the same bin are merged for
+// a few rounds (leader lane adds the popcount of its ballot); the remaining lanes
+// add 1 each.  Integer atomics make the result exact and order independent.
+__global__ __launch_bounds__(256) void bin_events(const uint2* __restrict__ ev, unsigned long long n,
+                                                  uint32_t* __restrict__ hist,
+                                                  unsigned long long* __restrict__ dropped, int npix,
+                                                  int nt, uint32_t bin_ps, uint32_t t0) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long stride = (unsigned long long)gridDim.x * 256ull;
+  unsigned int drop = 0;
+  for (unsigned long long base = (unsigned long long)blockIdx.x * 256ull + (threadIdx.x & ~63u);
+       base < n; base += stride) {
+    const unsigned long long k = base + lane;
+    long long key = -1;
+    if (k < n) {
+      const uint2 e = ev[k];
+      const int pixel = (int)e.x;
+      const uint32_t t = e.y;
+      if (pixel >= 0 && pixel < npix && t >= t0) {
+        const uint32_t b = (t - t0) / bin_ps;
+        if (b < (uint32_t)nt) key = (long long)pixel * nt + b;
+      }
+      if (key < 0) ++drop;
+    }
+    bool pending = key >= 0;
+#pragma unroll
+    for (int round = 0; round < 4; ++round) {
+      const unsigned long long m = __ballot(pending);
+      if (m == 0ull) break;
+      const int leader = __ffsll((long long)m) - 1;
+      const long long lk = __shfl(key, leader);
+      const bool same = pending && key == lk;
+      const unsigned long long sm = __ballot(same);
+      if (lane == leader) atomicAdd(hist + lk, (uint32_t)__popcll(sm));
+      if (same) pending = false;
+    }
+    if (pending) atomicAdd(hist + key, 1u);
+  }
+  if (dropped != nullptr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+    if (lane == 0 && drop != 0) atomicAdd(dropped, (unsigned long long)drop);
+  }
+}
+
+hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
+                      unsigned long long* dropped, int npix, int nt, uint32_t bin_ps, uint32_t t0,
+                      hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  unsigned long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(bin_events, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const uint2*>(events), n, hist, dropped, npix, nt, bin_ps, t0);
+  return hipGetLastError();
+}
+
+}  // namespace nlos

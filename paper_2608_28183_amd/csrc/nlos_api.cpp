@@ -1,0 +1,540 @@
+// Host side of libnlos: contexts, plans, validation, plan-time tables and the
+// pass schedules of nlos_bin / nlos_fk / nlos_rsd.  See include/nlos.h.
+#include "nlos.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "nlos_internal.hpp"
+#include "rsd_host.hpp"
+
+using nlos::ContigArgs;
+using nlos::FkColumnArgs;
+using nlos::StridedArgs;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+thread_local std::string g_err;  // failures without a context
+
+bool is_pow2_in(long long n, long long lo, long long hi) {
+  return n >= lo && n <= hi && (n & (n - 1)) == 0;
+}
+
+}  // namespace
+
+struct nlos_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float2* d_tw = nullptr;     // W_2048^k, FP64-generated, stored FP32
+  void* pool = nullptr;       // workspace when the caller passes none
+  size_t pool_bytes = 0;
+  std::string err;
+};
+
+struct nlos_fk_plan {
+  nlos_fk_desc d{};
+  int device = 0;
+  int Mx = 0, My = 0, Mt = 0;
+  double sxk = 0, syk = 0;
+  float norm = 0.f;
+};
+
+struct nlos_rsd_plan {
+  nlos_rsd_desc d{};
+  int device = 0;
+  int Mx = 0, My = 0;
+  nlos::RsdGeometry g{};
+  void* d_kr = nullptr;       // [Nrho][Nf][Nd] float2 or __half2
+  float* d_rho = nullptr;     // [My][Mx]
+  float2* d_w = nullptr;      // [Nf]
+  int* d_bins = nullptr;      // [Nf]
+};
+
+static nlos_status fail(nlos_ctx* ctx, nlos_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                   \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE, \
+                  "%s: %s", #call, hipGetErrorString(e_));                                    \
+  } while (0)
+
+extern "C" {
+
+int nlos_version(void) { return 100; }
+
+const char* nlos_status_string(nlos_status s) {
+  switch (s) {
+    case NLOS_OK: return "NLOS_OK";
+    case NLOS_ERR_INVALID_ARG: return "NLOS_ERR_INVALID_ARG";
+    case NLOS_ERR_UNSUPPORTED: return "NLOS_ERR_UNSUPPORTED";
+    case NLOS_ERR_OUT_OF_MEMORY: return "NLOS_ERR_OUT_OF_MEMORY";
+    case NLOS_ERR_DEVICE: return "NLOS_ERR_DEVICE";
+    case NLOS_ERR_INTERNAL: return "NLOS_ERR_INTERNAL";
+  }
+  return "NLOS_ERR_UNKNOWN";
+}
+
+const char* nlos_last_error(const nlos_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+nlos_status nlos_create(int device, void* hip_stream, nlos_ctx** out) {
+  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: no HIP device");
+  if (device < 0 || device >= count)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: device %d of %d", device, count);
+  if (hipSetDevice(device) != hipSuccess)
+    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: hipSetDevice(%d) failed", device);
+  nlos_ctx* c = new (std::nothrow) nlos_ctx();
+  if (!c) return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: host allocation");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  // W_2048^k = exp(-2 pi i k / 2048) in double with exact octant reduction, stored as float
+  std::vector<float2> tw(nlos::kTwiddleTableN);
+  for (int k = 0; k < nlos::kTwiddleTableN; ++k) {
+    double cs, sn;
+    nlos::cos_sin_2pi_frac(k, nlos::kTwiddleTableN, &cs, &sn);
+    tw[k] = make_float2((float)cs, (float)-sn);
+  }
+  if (hipMalloc(&c->d_tw, tw.size() * sizeof(float2)) != hipSuccess) {
+    delete c;
+    return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: twiddle table allocation");
+  }
+  if (hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c->d_tw);
+    delete c;
+    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: twiddle upload failed");
+  }
+  *out = c;
+  return NLOS_OK;
+}
+
+nlos_status nlos_destroy(nlos_ctx* ctx) {
+  if (!ctx) return NLOS_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->pool) (void)hipFree(ctx->pool);
+  if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+  delete ctx;
+  return NLOS_OK;
+}
+
+nlos_status nlos_set_stream(nlos_ctx* ctx, void* hip_stream) {
+  if (!ctx) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_set_stream: ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return NLOS_OK;
+}
+
+static nlos_status get_workspace(nlos_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, void** out) {
+  if (d_ws) {
+    if (ws_bytes < need)
+      return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    *out = d_ws;
+    return NLOS_OK;
+  }
+  if (ctx->pool_bytes < need) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->pool) HIP_TRY(ctx, hipFree(ctx->pool));
+    ctx->pool = nullptr;
+    ctx->pool_bytes = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->pool, need));
+    ctx->pool_bytes = need;
+  }
+  *out = ctx->pool;
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+
+nlos_status nlos_bin_check(const nlos_bin_desc* d) {
+  if (!d) return fail(nullptr, NLOS_ERR_INVALID_ARG, "bin: desc is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nt < 1)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "bin: dims must be >= 1 (%d %d %d)", d->nx, d->ny, d->nt);
+  if ((long long)d->nx * d->ny > 0x7fffffffLL ||
+      (long long)d->nx * d->ny * (long long)d->nt > (1LL << 40))
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "bin: histogram too large");
+  if (d->bin_ps < 1) return fail(nullptr, NLOS_ERR_INVALID_ARG, "bin: bin_ps must be >= 1");
+  if (d->accumulate != 0 && d->accumulate != 1)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "bin: accumulate must be 0 or 1");
+  return NLOS_OK;
+}
+
+nlos_status nlos_bin(nlos_ctx* ctx, const nlos_bin_desc* d, const nlos_event* d_events,
+                     uint64_t n_events, uint32_t* d_hist, unsigned long long* d_dropped) {
+  if (!ctx) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_bin: ctx is NULL");
+  nlos_status st = nlos_bin_check(d);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  if (!d_hist) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_bin: d_hist is NULL");
+  if (n_events > 0 && !d_events) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_bin: d_events is NULL");
+  if (reinterpret_cast<uintptr_t>(d_events) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_bin: d_events must be 8-byte aligned");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const size_t nbins = (size_t)d->nx * d->ny * d->nt;
+  if (!d->accumulate) {
+    HIP_TRY(ctx, nlos::launch_fill_u32(d_hist, nbins, 0u, ctx->stream));
+    if (d_dropped)
+      HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_dropped), 2, 0u, ctx->stream));
+  }
+  HIP_TRY(ctx, nlos::launch_bin(d_events, n_events, d_hist, d_dropped, d->nx * d->ny, d->nt, d->bin_ps,
+                                d->t0_ps, ctx->stream));
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// f-k
+// ---------------------------------------------------------------------------
+
+nlos_status nlos_fk_check(const nlos_fk_desc* d) {
+  if (!d) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: desc is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nt < 2)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: need nx, ny >= 1 and nt >= 2 (%d %d %d)", d->nx,
+                d->ny, d->nt);
+  if (d->pad != 1 && d->pad != 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: pad must be 1 or 2");
+  if (!(d->wall_w_m > 0) || !(d->wall_h_m > 0) || !(d->bin_ps > 0) || !std::isfinite(d->wall_w_m) ||
+      !std::isfinite(d->wall_h_m) || !std::isfinite(d->bin_ps))
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: wall size and bin width must be positive");
+  if (d->prec != NLOS_FP32 && d->prec != NLOS_FP16 && d->prec != NLOS_BF16)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bad precision %d", (int)d->prec);
+  const long long p = d->pad;
+  if (!is_pow2_in(p * d->nx, 8, 2048) || !is_pow2_in(p * d->ny, 8, 2048) ||
+      !is_pow2_in(p * d->nt, 8, 2048))
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED,
+                "fk: padded sizes %lld x %lld x %lld must be powers of two in [8, 2048]", p * d->ny,
+                p * d->nx, p * d->nt);
+  if (d->prec != NLOS_FP32)
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "fk: only FP32 storage is built");
+  return NLOS_OK;
+}
+
+nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
+  nlos_status st = nlos_fk_check(d);
+  if (st != NLOS_OK) return st;
+  if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bytes is NULL");
+  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny, nt = d->nt;
+  // W1 [ny][Mx][nt] + W2 [My][Mx][nt], complex float
+  *bytes = (size_t)d->ny * Mx * nt * 8 + My * Mx * nt * 8;
+  return NLOS_OK;
+}
+
+nlos_status nlos_fk_plan_create(nlos_ctx* ctx, const nlos_fk_desc* d, nlos_fk_plan** out) {
+  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "fk_plan_create: NULL argument");
+  nlos_status st = nlos_fk_check(d);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  nlos_fk_plan* p = new (std::nothrow) nlos_fk_plan();
+  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "fk_plan_create: host allocation");
+  p->d = *d;
+  p->device = ctx->device;
+  p->Mx = d->pad * d->nx;
+  p->My = d->pad * d->ny;
+  p->Mt = d->pad * d->nt;
+  const double c_dt = kC * d->bin_ps * 1e-12;
+  const double sx = c_dt / (2.0 * (d->wall_w_m / d->nx));
+  const double sy = c_dt / (2.0 * (d->wall_h_m / d->ny));
+  p->sxk = sx * (double)p->Mt / (double)p->Mx;
+  p->syk = sy * (double)p->Mt / (double)p->My;
+  p->norm = (float)(1.0 / ((double)p->Mx * (double)p->My * (double)p->Mt));
+  *out = p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_fk_plan_destroy(nlos_fk_plan* p) {
+  delete p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_vol, float* d_img,
+                    void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: ctx or plan is NULL");
+  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau is NULL");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: plan of another device");
+  const nlos_fk_desc& d = p->d;
+  size_t need = 0;
+  nlos_status st = nlos_fk_workspace_bytes(&d, &need);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
+  if (st != NLOS_OK) return st;
+  const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
+  float2* W1 = static_cast<float2*>(ws);             // [ny][Mx][nt]
+  float2* W2 = W1 + (size_t)ny * Mx * nt;            // [My][Mx][nt]
+  hipStream_t s = ctx->stream;
+  const float2* tw = ctx->d_tw;
+  if (d_img) HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s));
+
+  StridedArgs a{};
+  // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx
+  a.in = d_tau; a.out = W1;
+  a.in_plane = nx * nt; a.in_line = nt; a.out_plane = Mx * nt; a.out_line = nt;
+  a.ncols = (int)nt; a.n_in = (int)nx; a.n_out = (int)Mx;
+  a.tscale = (float)(1.0 / (double)(nt - 1));
+  HIP_TRY(ctx, nlos::launch_strided((int)Mx, false, nlos::LD_TAU_SCALED, nlos::ST_C64, a, (int)ny, tw, s));
+  // pass 2: y-FFT, zero padded to My
+  a = StridedArgs{};
+  a.in = W1; a.out = W2;
+  a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
+  a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
+  HIP_TRY(ctx, nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s));
+  // pass 3: per (ky, kx) column: t-FFT, Stolt + Jacobian + 1/(Mx My Mt), z-IFFT, keep z < nt
+  FkColumnArgs c{};
+  c.W = W2; c.ncols = My * Mx; c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
+  c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
+  HIP_TRY(ctx, nlos::launch_fk_column(p->Mt, c, tw, s));
+  // pass 4: y-IFFT, keep y < ny
+  a = StridedArgs{};
+  a.in = W2; a.out = W1;
+  a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
+  a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
+  HIP_TRY(ctx, nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s));
+  // pass 5: x-IFFT, keep x < nx, |Psi|^2 and the max over depth
+  a = StridedArgs{};
+  a.in = W1; a.out = d_vol;
+  a.in_plane = Mx * nt; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
+  a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
+  a.oscale = 1.0f; a.img = d_img; a.img_plane = nx;
+  HIP_TRY(ctx, nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS2_IMG, a, (int)ny, tw, s));
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// RSD
+// ---------------------------------------------------------------------------
+
+static nlos::RsdInputs rsd_inputs(const nlos_rsd_desc* d) {
+  nlos::RsdInputs in;
+  in.nx = d->nx; in.ny = d->ny; in.nt = d->nt; in.pad = d->pad;
+  in.dx = d->dx_m; in.dy = d->dy_m; in.c_dt = kC * d->bin_ps * 1e-12;
+  in.n_freq = d->n_freq; in.freq_bin = d->freq_bin;
+  in.n_depth = d->n_depth; in.depth0 = d->depth0_m; in.depth_step = d->depth_step_m;
+  in.sigma_s = d->sigma_s; in.sigma_t = d->sigma_t; in.delta = d->delta_m;
+  return in;
+}
+
+nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
+  if (!d) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: desc is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nt < 1)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: dims must be >= 1");
+  if (d->pad != 1 && d->pad != 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: pad must be 1 or 2");
+  if (!(d->dx_m > 0) || !(d->dy_m > 0) || !(d->bin_ps > 0) || !std::isfinite(d->dx_m) ||
+      !std::isfinite(d->dy_m) || !std::isfinite(d->bin_ps))
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: spacings must be positive");
+  if (d->n_freq < 1 || !d->freq_bin || !d->w)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: need n_freq >= 1, freq_bin and w");
+  if (d->n_depth < 1 || d->n_depth > 4096)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: n_depth must be in [1, 4096]");
+  if (!std::isfinite(d->depth0_m) || !std::isfinite(d->depth_step_m) || !std::isfinite(d->delta_m))
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: depth grid must be finite");
+  if (d->sigma_s != 1 && d->sigma_s != 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: sigma_s must be 1 or 2");
+  if (d->sigma_t < 0 || d->sigma_t > 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: sigma_t must be 0, 1 or 2");
+  if (d->data_prec < NLOS_FP32 || d->data_prec > NLOS_BF16 || d->kernel_prec < NLOS_FP32 ||
+      d->kernel_prec > NLOS_BF16)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bad precision");
+  const long long p = d->pad;
+  if (!is_pow2_in(p * d->nx, 8, 2048) || !is_pow2_in(p * d->ny, 8, 2048) || !is_pow2_in(d->nt, 8, 2048))
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED,
+                "rsd: pad*nx, pad*ny and nt must be powers of two in [8, 2048]");
+  for (int f = 0; f < d->n_freq; ++f)
+    if (d->freq_bin[f] < 1 || d->freq_bin[f] > d->nt / 2 - 1)
+      return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: freq_bin[%d] = %d outside [1, nt/2 - 1]", f,
+                  d->freq_bin[f]);
+  for (int f = 0; f < 2 * d->n_freq; ++f)
+    if (!std::isfinite(d->w[f])) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: w is not finite");
+  if (d->data_prec != NLOS_FP32) return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: only FP32 data is built");
+  if (d->kernel_prec == NLOS_BF16)
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: kernel storage is FP32 or FP16");
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc* d, nlos_rsd_geometry* out) {
+  nlos_status st = nlos_rsd_check(d);
+  if (st != NLOS_OK) return st;
+  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_geometry_get: out is NULL");
+  const nlos::RsdGeometry g = nlos::rsd_geometry(rsd_inputs(d));
+  out->r_max = g.r_max; out->rho_max = g.rho_max; out->lambda_min = g.lambda_min; out->dr = g.dr;
+  out->f_s = g.f_s; out->rho_cut = g.rho_cut; out->rho_cut_bin = g.rho_cut_bin;
+  out->n_r_min = g.n_r_min; out->n_r = g.n_r; out->n_rho_min = g.n_rho_min; out->n_rho = g.n_rho;
+  out->cut_idx = g.cut_idx; out->last_base = g.last_base;
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_kernel_host(const nlos_rsd_desc* d, float* out, size_t n_floats) {
+  nlos_status st = nlos_rsd_check(d);
+  if (st != NLOS_OK) return st;
+  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: out is NULL");
+  const nlos::RsdInputs in = rsd_inputs(d);
+  const nlos::RsdGeometry g = nlos::rsd_geometry(in);
+  const size_t need = 2ull * g.n_rho * d->n_freq * d->n_depth;
+  if (n_floats < need) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: need %zu floats", need);
+  std::vector<double> re, im;
+  nlos::rsd_radial_kernel(in, g, re, im);
+  for (size_t i = 0; i < re.size(); ++i) {
+    out[2 * i] = (float)re[i];
+    out[2 * i + 1] = (float)im[i];
+  }
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc* d, size_t* bytes) {
+  nlos_status st = nlos_rsd_check(d);
+  if (st != NLOS_OK) return st;
+  if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bytes is NULL");
+  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny;
+  const size_t nf = d->n_freq, nd = d->n_depth, ny = d->ny;
+  // A [max(Nf,Nd)][ny][Mx] + B [Nf][My][Mx] + C [Nd][My][Mx], complex float
+  *bytes = (std::max(nf, nd) * ny * Mx + nf * My * Mx + nd * My * Mx) * 8;
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan* p) {
+  if (!p) return NLOS_OK;
+  (void)hipSetDevice(p->device);
+  if (p->d_kr) (void)hipFree(p->d_kr);
+  if (p->d_rho) (void)hipFree(p->d_rho);
+  if (p->d_w) (void)hipFree(p->d_w);
+  if (p->d_bins) (void)hipFree(p->d_bins);
+  delete p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd_plan** out) {
+  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "rsd_plan_create: NULL argument");
+  nlos_status st = nlos_rsd_check(d);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  nlos_rsd_plan* p = new (std::nothrow) nlos_rsd_plan();
+  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "rsd_plan_create: host allocation");
+  p->d = *d;
+  p->d.freq_bin = nullptr;  // host arrays are copied to the device below
+  p->d.w = nullptr;
+  p->device = ctx->device;
+  p->Mx = d->pad * d->nx;
+  p->My = d->pad * d->ny;
+  const nlos::RsdInputs in = rsd_inputs(d);
+  p->g = nlos::rsd_geometry(in);
+  std::vector<double> kre, kim;
+  nlos::rsd_radial_kernel(in, p->g, kre, kim);
+  std::vector<float> rho;
+  nlos::rsd_radius_map(in, p->g, rho);
+  const size_t nk = kre.size();
+  auto cleanup = [&](nlos_status s, const char* what, hipError_t e) {
+    nlos_rsd_plan_destroy(p);
+    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : s, "rsd_plan_create: %s: %s", what,
+                hipGetErrorString(e));
+  };
+  hipError_t e;
+  if (d->kernel_prec == NLOS_FP16) {
+    // FP64 accumulation, a single rounding to binary16 on store
+    std::vector<_Float16> kh(2 * nk);
+    for (size_t i = 0; i < nk; ++i) {
+      kh[2 * i] = (_Float16)kre[i];
+      kh[2 * i + 1] = (_Float16)kim[i];
+    }
+    if ((e = hipMalloc(&p->d_kr, nk * 4)) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
+    if ((e = hipMemcpy(p->d_kr, kh.data(), nk * 4, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
+  } else {
+    std::vector<float2> kf(nk);
+    for (size_t i = 0; i < nk; ++i) kf[i] = make_float2((float)kre[i], (float)kim[i]);
+    if ((e = hipMalloc(&p->d_kr, nk * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
+    if ((e = hipMemcpy(p->d_kr, kf.data(), nk * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
+  }
+  if ((e = hipMalloc(&p->d_rho, rho.size() * sizeof(float))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "rho", e);
+  if ((e = hipMemcpy(p->d_rho, rho.data(), rho.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(NLOS_ERR_DEVICE, "rho upload", e);
+  std::vector<float2> w(d->n_freq);
+  for (int f = 0; f < d->n_freq; ++f) w[f] = make_float2(d->w[2 * f], d->w[2 * f + 1]);
+  if ((e = hipMalloc(&p->d_w, w.size() * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "w", e);
+  if ((e = hipMemcpy(p->d_w, w.data(), w.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(NLOS_ERR_DEVICE, "w upload", e);
+  std::vector<int> bins(d->freq_bin, d->freq_bin + d->n_freq);
+  if ((e = hipMalloc(&p->d_bins, bins.size() * sizeof(int))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "bins", e);
+  if ((e = hipMemcpy(p->d_bins, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(NLOS_ERR_DEVICE, "bins upload", e);
+  *out = p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, float* d_vol, float* d_img,
+                     void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: ctx or plan is NULL");
+  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_tau is NULL");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: plan of another device");
+  const nlos_rsd_desc& d = p->d;
+  const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
+  const long long Nf = d.n_freq, Nd = d.n_depth;
+  const size_t need = ((size_t)std::max(Nf, Nd) * ny * Mx + (size_t)Nf * My * Mx + (size_t)Nd * My * Mx) * 8;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
+  if (st != NLOS_OK) return st;
+  float2* A = static_cast<float2*>(ws);                      // [max(Nf,Nd)][ny][Mx]
+  float2* B = A + (size_t)std::max(Nf, Nd) * ny * Mx;        // [Nf][My][Mx]
+  float2* C = B + (size_t)Nf * My * Mx;                      // [Nd][My][Mx]
+  hipStream_t s = ctx->stream;
+  const float2* tw = ctx->d_tw;
+  if (d_img) HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s));
+
+  // 1. phasors: t-FFT of each pixel, bins k_f -> A[f][y][x] (row stride Mx)
+  ContigArgs c{};
+  c.in = d_tau; c.out = A; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
+  c.bins = p->d_bins; c.nbins = (int)Nf; c.out_fstride = ny * Mx; c.row_in = nx; c.row_out = Mx;
+  HIP_TRY(ctx, nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s));
+  // 2. x-FFT of the top-left padded planes, in place in A
+  c = ContigArgs{};
+  c.in = A; c.out = A; c.nlines = Nf * ny; c.in_line = Mx; c.out_line = Mx; c.n_in = (int)nx; c.n_out = (int)Mx;
+  HIP_TRY(ctx, nlos::launch_contig((int)Mx, false, nlos::CL_C64, nlos::CS_C64, c, tw, s));
+  // 3. y-FFT: A -> B[f][My][Mx]
+  StridedArgs a{};
+  a.in = A; a.out = B; a.in_plane = ny * Mx; a.in_line = Mx; a.out_plane = My * Mx; a.out_line = Mx;
+  a.ncols = (int)Mx; a.n_in = (int)ny; a.n_out = (int)My;
+  HIP_TRY(ctx, nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Nf, tw, s));
+  // 4. radial propagation: B -> C[d][My][Mx]
+  nlos::RsdPropArgs r{};
+  r.Ph = B; r.Kr = p->d_kr; r.rho = p->d_rho; r.w = p->d_w; r.C = C; r.npix = My * Mx;
+  r.Nf = (int)Nf; r.Nd = (int)Nd; r.rho_cut_bin = (float)p->g.rho_cut_bin; r.cut_idx = p->g.cut_idx;
+  r.last_base = p->g.last_base; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
+  HIP_TRY(ctx, nlos::launch_rsd_propagate(r, s));
+  // 5. y-IFFT, keep y < ny: C -> A[d][ny][Mx]
+  a = StridedArgs{};
+  a.in = C; a.out = A; a.in_plane = My * Mx; a.in_line = Mx; a.out_plane = ny * Mx; a.out_line = Mx;
+  a.ncols = (int)Mx; a.n_in = (int)My; a.n_out = (int)ny;
+  HIP_TRY(ctx, nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Nd, tw, s));
+  // 6. x-IFFT, keep x < nx, |I| / (Mx My) and the max over depth
+  c = ContigArgs{};
+  c.in = A; c.out = d_vol; c.nlines = Nd * ny; c.in_line = Mx; c.out_line = nx; c.n_in = (int)Mx;
+  c.n_out = (int)nx; c.oscale = (float)(1.0 / ((double)Mx * (double)My)); c.img = d_img; c.img_lines = ny;
+  HIP_TRY(ctx, nlos::launch_contig((int)Mx, true, nlos::CL_C64, nlos::CS_ABS_IMG, c, tw, s));
+  return NLOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host API (nlos_api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nlos {
+
+// strided_fft load / store modes
+enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
+enum { ST_C64 = 0, ST_ABS2_IMG = 1 };
+// contig_fft load / store modes
+enum { CL_C64 = 0, CL_REAL = 1 };
+enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2 };
+
+// Lines along a strided axis.  Element n of line `col` in plane `plane` is at
+// in[plane * in_plane + n * in_line + col]; n < n_in are read (the rest are the
+// zero padding), n < n_out are written.
+struct StridedArgs {
+  const void* in;
+  void* out;
+  long long in_plane, in_line;
+  long long out_plane, out_line;
+  int ncols, n_in, n_out;
+  float tscale;        // LD_TAU_SCALED: the sample in column t is scaled by t * tscale
+  float oscale;        // ST_ABS2_IMG: output = |v|^2 * oscale
+  float* img;          // ST_ABS2_IMG: img[plane * img_plane + n] = max over columns (may be null)
+  long long img_plane;
+};
+
+// Lines along the contiguous axis: line `ln` is in[ln * in_line + n], n < n_in.
+struct ContigArgs {
+  const void* in;
+  void* out;
+  long long nlines, in_line, out_line;
+  int n_in, n_out;
+  float oscale;        // CS_ABS_IMG: output = |v| * oscale
+  float* img;          // CS_ABS_IMG: img[(ln % img_lines) * out_line + n] = max over lines
+  long long img_lines;
+  const int* bins;     // CS_BINS: out[f * out_fstride + y * row_out + x] = X[bins[f]],
+  int nbins;           //          line ln = y * row_in + x
+  long long out_fstride;
+  long long row_in, row_out;
+};
+
+// f-k column pass over W[ncols][nt] (column = ky * Mx + kx), in place.
+struct FkColumnArgs {
+  float2* W;
+  long long ncols;
+  int nt, Mx, My;
+  double sxk, syk;     // Stolt coordinate per signed kx, ky in units of the t bins
+  float norm;          // 1 / (Mx My Mt)
+};
+
+struct RsdPropArgs {
+  const float2* Ph;    // [Nf][npix] spectra of the padded phasor planes
+  const void* Kr;      // [Nrho][Nf][Nd] radial kernel, float2 or __half2
+  const float* rho;    // [npix] pixel-to-radius map in bin units
+  const float2* w;     // [Nf] complex frequency weights
+  float2* C;           // [Nd][npix] propagated spectra
+  long long npix;
+  int Nf, Nd;
+  float rho_cut_bin;
+  int cut_idx, last_base;
+  int kernel_fp16;
+};
+
+hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
+                          const float2* tw, hipStream_t s);
+hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a,
+                         const float2* tw, hipStream_t s);
+hipError_t launch_fk_column(int n, const FkColumnArgs& a, const float2* tw, hipStream_t s);
+hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
+hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
+                      unsigned long long* dropped, int npix, int nt, uint32_t bin_ps, uint32_t t0,
+                      hipStream_t s);
+
+}  // namespace nlos

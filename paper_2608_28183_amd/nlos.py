@@ -1,0 +1,291 @@
+"""Python binding of libnlos (include/nlos.h): argument marshalling only.
+
+Every ``nlos_*`` function here calls the C entry point of the same name.  Device
+buffers are passed as torch tensors on the context's device (only their
+``data_ptr()`` crosses the ABI) and streams as ``torch.cuda.Stream``.  Nothing
+is computed in Python; if ``libnlos.so`` is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlos.so")
+
+NLOS_OK = 0
+NLOS_ERR_INVALID_ARG = 1
+NLOS_ERR_UNSUPPORTED = 2
+NLOS_ERR_OUT_OF_MEMORY = 3
+NLOS_ERR_DEVICE = 4
+NLOS_ERR_INTERNAL = 5
+
+NLOS_FP32 = 0
+NLOS_FP16 = 1
+NLOS_BF16 = 2
+PRECISIONS = {"fp32": NLOS_FP32, "fp16": NLOS_FP16, "bf16": NLOS_BF16}
+
+
+class NlosError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        self.status = status
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+STATUS_NAMES = {0: "NLOS_OK", 1: "NLOS_ERR_INVALID_ARG", 2: "NLOS_ERR_UNSUPPORTED",
+                3: "NLOS_ERR_OUT_OF_MEMORY", 4: "NLOS_ERR_DEVICE", 5: "NLOS_ERR_INTERNAL"}
+
+
+class nlos_bin_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nt", ctypes.c_int),
+                ("bin_ps", ctypes.c_uint32), ("t0_ps", ctypes.c_uint32),
+                ("accumulate", ctypes.c_int)]
+
+
+class nlos_fk_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nt", ctypes.c_int),
+                ("wall_w_m", ctypes.c_double), ("wall_h_m", ctypes.c_double),
+                ("bin_ps", ctypes.c_double), ("pad", ctypes.c_int), ("prec", ctypes.c_int)]
+
+
+class nlos_rsd_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nt", ctypes.c_int),
+                ("dx_m", ctypes.c_double), ("dy_m", ctypes.c_double), ("bin_ps", ctypes.c_double),
+                ("pad", ctypes.c_int), ("n_freq", ctypes.c_int),
+                ("freq_bin", ctypes.POINTER(ctypes.c_int32)), ("w", ctypes.POINTER(ctypes.c_float)),
+                ("n_depth", ctypes.c_int), ("depth0_m", ctypes.c_double),
+                ("depth_step_m", ctypes.c_double), ("sigma_s", ctypes.c_int),
+                ("sigma_t", ctypes.c_int), ("delta_m", ctypes.c_double),
+                ("data_prec", ctypes.c_int), ("kernel_prec", ctypes.c_int)]
+
+
+class nlos_rsd_geometry(ctypes.Structure):
+    _fields_ = [("r_max", ctypes.c_double), ("rho_max", ctypes.c_double),
+                ("lambda_min", ctypes.c_double), ("dr", ctypes.c_double), ("f_s", ctypes.c_double),
+                ("rho_cut", ctypes.c_double), ("rho_cut_bin", ctypes.c_double),
+                ("n_r_min", ctypes.c_int), ("n_r", ctypes.c_int), ("n_rho_min", ctypes.c_int),
+                ("n_rho", ctypes.c_int), ("cut_idx", ctypes.c_int), ("last_base", ctypes.c_int)]
+
+
+_VP = ctypes.c_void_p
+_ST = ctypes.c_int
+_SIGNATURES = {
+    "nlos_version": (ctypes.c_int, []),
+    "nlos_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "nlos_last_error": (ctypes.c_char_p, [_VP]),
+    "nlos_create": (_ST, [ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
+    "nlos_destroy": (_ST, [_VP]),
+    "nlos_set_stream": (_ST, [_VP, _VP]),
+    "nlos_bin_check": (_ST, [ctypes.POINTER(nlos_bin_desc)]),
+    "nlos_bin": (_ST, [_VP, ctypes.POINTER(nlos_bin_desc), _VP, ctypes.c_uint64, _VP, _VP]),
+    "nlos_fk_check": (_ST, [ctypes.POINTER(nlos_fk_desc)]),
+    "nlos_fk_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_fk_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(_VP)]),
+    "nlos_fk_plan_destroy": (_ST, [_VP]),
+    "nlos_fk": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_rsd_check": (_ST, [ctypes.POINTER(nlos_rsd_desc)]),
+    "nlos_rsd_geometry_get": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(nlos_rsd_geometry)]),
+    "nlos_rsd_kernel_host": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_float),
+                                   ctypes.c_size_t]),
+    "nlos_rsd_workspace_bytes": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_rsd_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(_VP)]),
+    "nlos_rsd_plan_destroy": (_ST, [_VP]),
+    "nlos_rsd": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libnlos.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2608_28183_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status: int, func: str, ctx=None) -> None:
+    if status != NLOS_OK:
+        detail = lib().nlos_last_error(ctx).decode(errors="replace")
+        raise NlosError(status, func, detail)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+def nlos_version() -> int:
+    return lib().nlos_version()
+
+
+def nlos_status_string(status: int) -> str:
+    return lib().nlos_status_string(status).decode()
+
+
+def nlos_create(device: int = 0, stream=None) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().nlos_create(device, _stream_handle(stream), ctypes.byref(out)), "nlos_create")
+    return out.value
+
+
+def nlos_destroy(ctx: int) -> None:
+    _check(lib().nlos_destroy(ctx), "nlos_destroy")
+
+
+def nlos_set_stream(ctx: int, stream) -> None:
+    _check(lib().nlos_set_stream(ctx, _stream_handle(stream)), "nlos_set_stream", ctx)
+
+
+def nlos_last_error(ctx: Optional[int] = None) -> str:
+    return lib().nlos_last_error(ctx).decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# binning
+# ---------------------------------------------------------------------------
+
+def bin_desc(nx: int, ny: int, nt: int, bin_ps: int, t0_ps: int = 0,
+             accumulate: bool = False) -> nlos_bin_desc:
+    return nlos_bin_desc(nx, ny, nt, bin_ps, t0_ps, int(accumulate))
+
+
+def nlos_bin_check(desc: nlos_bin_desc) -> int:
+    return lib().nlos_bin_check(ctypes.byref(desc))
+
+
+def nlos_bin(ctx: int, desc: nlos_bin_desc, events, n_events: int, hist, dropped=None) -> None:
+    """events: uint8/int32 tensor holding n_events packed (int32 pixel, uint32 t_ps) records;
+    hist: int32 tensor [ny, nx, nt] (uint32 counts); dropped: int64 tensor [1] or None."""
+    _check(lib().nlos_bin(ctx, ctypes.byref(desc), _ptr(events), n_events, _ptr(hist),
+                          _ptr(dropped)), "nlos_bin", ctx)
+
+
+# ---------------------------------------------------------------------------
+# f-k
+# ---------------------------------------------------------------------------
+
+def fk_desc(nx: int, ny: int, nt: int, wall_w_m: float, wall_h_m: float, bin_ps: float,
+            pad: int = 2, prec: str = "fp32") -> nlos_fk_desc:
+    return nlos_fk_desc(nx, ny, nt, wall_w_m, wall_h_m, bin_ps, pad, PRECISIONS[prec])
+
+
+def nlos_fk_check(desc: nlos_fk_desc) -> int:
+    return lib().nlos_fk_check(ctypes.byref(desc))
+
+
+def nlos_fk_workspace_bytes(desc: nlos_fk_desc) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().nlos_fk_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)),
+           "nlos_fk_workspace_bytes")
+    return out.value
+
+
+def nlos_fk_plan_create(ctx: int, desc: nlos_fk_desc) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().nlos_fk_plan_create(ctx, ctypes.byref(desc), ctypes.byref(out)),
+           "nlos_fk_plan_create", ctx)
+    return out.value
+
+
+def nlos_fk_plan_destroy(plan: int) -> None:
+    _check(lib().nlos_fk_plan_destroy(plan), "nlos_fk_plan_destroy")
+
+
+def nlos_fk(ctx: int, plan: int, tau, vol=None, img=None, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_fk(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
+           "nlos_fk", ctx)
+
+
+# ---------------------------------------------------------------------------
+# RSD
+# ---------------------------------------------------------------------------
+
+class RsdDesc:
+    """nlos_rsd_desc plus the host arrays it points to (kept alive here)."""
+
+    def __init__(self, nx, ny, nt, dx_m, dy_m, bin_ps, pad, freq_bins: Sequence[int], weights,
+                 n_depth, depth0_m, depth_step_m, sigma_s=2, sigma_t=0, delta_m=0.0,
+                 data_prec="fp32", kernel_prec="fp32"):
+        n = len(freq_bins)
+        self._bins = (ctypes.c_int32 * n)(*[int(k) for k in freq_bins])
+        wf = []
+        for w in weights:
+            wf += [float(complex(w).real), float(complex(w).imag)]
+        self._w = (ctypes.c_float * (2 * n))(*wf)
+        self.c = nlos_rsd_desc(nx, ny, nt, dx_m, dy_m, bin_ps, pad, n,
+                               ctypes.cast(self._bins, ctypes.POINTER(ctypes.c_int32)),
+                               ctypes.cast(self._w, ctypes.POINTER(ctypes.c_float)),
+                               n_depth, depth0_m, depth_step_m, sigma_s, sigma_t, delta_m,
+                               PRECISIONS[data_prec], PRECISIONS[kernel_prec])
+
+
+def nlos_rsd_check(desc: RsdDesc) -> int:
+    return lib().nlos_rsd_check(ctypes.byref(desc.c))
+
+
+def nlos_rsd_geometry_get(desc: RsdDesc) -> dict:
+    g = nlos_rsd_geometry()
+    _check(lib().nlos_rsd_geometry_get(ctypes.byref(desc.c), ctypes.byref(g)), "nlos_rsd_geometry_get")
+    return {name: getattr(g, name) for name, _ in g._fields_}
+
+
+def nlos_rsd_kernel_host(desc: RsdDesc):
+    """K_r[n_rho][n_freq][n_depth] as complex64 numpy array, built on the host."""
+    import numpy as np
+    g = nlos_rsd_geometry_get(desc)
+    n = 2 * g["n_rho"] * desc.c.n_freq * desc.c.n_depth
+    out = np.zeros(n, dtype=np.float32)
+    _check(lib().nlos_rsd_kernel_host(ctypes.byref(desc.c),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n),
+           "nlos_rsd_kernel_host")
+    return out.view(np.complex64).reshape(g["n_rho"], desc.c.n_freq, desc.c.n_depth)
+
+
+def nlos_rsd_workspace_bytes(desc: RsdDesc) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().nlos_rsd_workspace_bytes(ctypes.byref(desc.c), ctypes.byref(out)),
+           "nlos_rsd_workspace_bytes")
+    return out.value
+
+
+def nlos_rsd_plan_create(ctx: int, desc: RsdDesc) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().nlos_rsd_plan_create(ctx, ctypes.byref(desc.c), ctypes.byref(out)),
+           "nlos_rsd_plan_create", ctx)
+    return out.value
+
+
+def nlos_rsd_plan_destroy(plan: int) -> None:
+    _check(lib().nlos_rsd_plan_destroy(plan), "nlos_rsd_plan_destroy")
+
+
+def nlos_rsd(ctx: int, plan: int, tau, vol=None, img=None, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_rsd(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
+           "nlos_rsd", ctx)

@@ -1,0 +1,99 @@
+"""Tensor-level helpers over the C ABI: contexts, plans and workspace as torch
+device memory.  Marshalling only -- every step runs in libnlos kernels."""
+from __future__ import annotations
+
+import torch
+
+from . import nlos
+
+EVENT_BYTES = 8
+
+
+class Context:
+    """An nlos context bound to one device and stream."""
+
+    def __init__(self, device: int = 0, stream: "torch.cuda.Stream | None" = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libnlos needs a HIP device")
+        self.device = torch.device("cuda", device)
+        self.stream = stream
+        self.handle = nlos.nlos_create(device, stream)
+
+    def set_stream(self, stream) -> None:
+        self.stream = stream
+        nlos.nlos_set_stream(self.handle, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            nlos.nlos_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FkPlan:
+    def __init__(self, ctx: Context, ny: int, nx: int, nt: int, wall_w: float, wall_h: float,
+                 bin_ps: float, pad: int = 2, prec: str = "fp32"):
+        self.ctx = ctx
+        self.shape = (ny, nx, nt)
+        self.desc = nlos.fk_desc(nx, ny, nt, wall_w, wall_h, bin_ps, pad, prec)
+        self.ws_bytes = nlos.nlos_fk_workspace_bytes(self.desc)
+        self.handle = nlos.nlos_fk_plan_create(ctx.handle, self.desc)
+
+    def workspace(self) -> torch.Tensor:
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
+
+    def __call__(self, tau: torch.Tensor, vol=None, img=None, ws=None):
+        ny, nx, nt = self.shape
+        assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
+        nlos.nlos_fk(self.ctx.handle, self.handle, tau, vol, img, ws)
+        return vol, img
+
+    def __del__(self):
+        try:
+            nlos.nlos_fk_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class RsdPlan:
+    def __init__(self, ctx: Context, ny: int, nx: int, nt: int, dx: float, dy: float, bin_ps: float,
+                 pad: int, freq_bins, weights, n_depth: int, depth0: float, depth_step: float,
+                 sigma_s: int = 2, sigma_t: int = 0, delta: float = 0.0, data_prec: str = "fp32",
+                 kernel_prec: str = "fp32"):
+        self.ctx = ctx
+        self.shape = (ny, nx, nt)
+        self.n_depth = n_depth
+        self.desc = nlos.RsdDesc(nx, ny, nt, dx, dy, bin_ps, pad, freq_bins, weights, n_depth,
+                                 depth0, depth_step, sigma_s, sigma_t, delta, data_prec,
+                                 kernel_prec)
+        self.ws_bytes = nlos.nlos_rsd_workspace_bytes(self.desc)
+        self.handle = nlos.nlos_rsd_plan_create(ctx.handle, self.desc)
+
+    def workspace(self) -> torch.Tensor:
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
+
+    def __call__(self, tau: torch.Tensor, vol=None, img=None, ws=None):
+        ny, nx, nt = self.shape
+        assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
+        nlos.nlos_rsd(self.ctx.handle, self.handle, tau, vol, img, ws)
+        return vol, img
+
+    def __del__(self):
+        try:
+            nlos.nlos_rsd_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def bin_events(ctx: Context, events: torch.Tensor, n_events: int, hist: torch.Tensor, bin_ps: int,
+               t0_ps: int = 0, accumulate: bool = False, dropped: "torch.Tensor | None" = None):
+    """events: device tensor of n_events packed 8-byte records; hist: int32 [ny, nx, nt]."""
+    ny, nx, nt = hist.shape
+    desc = nlos.bin_desc(nx, ny, nt, bin_ps, t0_ps, accumulate)
+    nlos.nlos_bin(ctx.handle, desc, events, n_events, hist, dropped)
+    return hist, dropped

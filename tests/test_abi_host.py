@@ -1,0 +1,138 @@
+"""The C-ABI library: exports, host-side validation and plan-time math (no GPU)."""
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import rsd as orsd
+from paper_2608_28183_amd import nlos
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "nlos.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nlos_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nlos.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert nlos.nlos_version() == 100
+    assert nlos.nlos_status_string(2) == "NLOS_ERR_UNSUPPORTED"
+
+
+def test_fk_validation():
+    ok = nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=2)
+    assert nlos.nlos_fk_check(ok) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=3)) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_fk_check(nlos.fk_desc(100, 256, 512, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(2048, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(1024, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(2, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(8, 8, 1, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_fk_check(nlos.fk_desc(8, 8, 8, -1.0, 1.0, 32.0)) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_fk_check(nlos.fk_desc(8, 8, 8, 1.0, 1.0, float("nan"))) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_fk_check(nlos.fk_desc(0, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_INVALID_ARG
+    assert "pad" in nlos.nlos_last_error() or nlos.nlos_last_error() != ""
+
+
+def test_fk_workspace_is_exact():
+    d = nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=2)
+    assert nlos.nlos_fk_workspace_bytes(d) == (256 * 512 * 512 + 512 * 512 * 512) * 8
+    d = nlos.fk_desc(32, 16, 64, 1.0, 1.0, 32.0, pad=1)
+    assert nlos.nlos_fk_workspace_bytes(d) == (16 * 32 * 64 + 16 * 32 * 64) * 8
+    with pytest.raises(nlos.NlosError):
+        nlos.nlos_fk_workspace_bytes(nlos.fk_desc(3, 8, 8, 1.0, 1.0, 32.0))
+
+
+def test_bin_validation():
+    assert nlos.nlos_bin_check(nlos.bin_desc(64, 64, 512, 16)) == nlos.NLOS_OK
+    assert nlos.nlos_bin_check(nlos.bin_desc(0, 64, 512, 16)) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_bin_check(nlos.bin_desc(64, 64, 512, 0)) == nlos.NLOS_ERR_INVALID_ARG
+    d = nlos.bin_desc(64, 64, 512, 16)
+    d.accumulate = 2
+    assert nlos.nlos_bin_check(d) == nlos.NLOS_ERR_INVALID_ARG
+
+
+def _rsd_desc(cfg, pad=2, n_depth=None, **kw):
+    p = scenes.rsd_params(cfg, n_depth)
+    return nlos.RsdDesc(cfg.nx, cfg.ny, cfg.nt, cfg.dx, cfg.dy, cfg.bin_ps, pad, p.freq_bins,
+                        p.weights, p.n_depth, p.depth0, p.depth_step, **kw), p
+
+
+def test_rsd_validation():
+    cfg = scenes.CONFIGS["c1"]
+    d, _ = _rsd_desc(cfg)
+    assert nlos.nlos_rsd_check(d) == nlos.NLOS_OK
+    bad, _ = _rsd_desc(cfg, pad=3)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG
+    bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [0, 5], [1, 1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG       # bin 0
+    bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5, 128], [1, 1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG       # bin nt/2
+    bad = nlos.RsdDesc(30, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED
+    bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 0, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG
+    bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01, sigma_s=3)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG
+
+
+def test_rsd_worked_example_through_the_library():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "rsd_worked_example.json")))
+    inp, exp = g["inputs"], g["expected"]
+    dx = math.sqrt(2.0) / (2.0 * inp["rho_max_per_m"])
+    n = inp["n"]
+    # a frequency bin whose wavelength is the printed lambda_min: nt c dt / k = 0.030 m
+    nt, k = 2048, 1000
+    bin_ps = inp["lambda_min_m"] * k / nt / scenes.C_LIGHT * 1e12
+    d = nlos.RsdDesc(n, n, nt, dx, dx, bin_ps, 1, [k], [1.0], 4, 0.5, 0.1, sigma_s=inp["sigma_s"],
+                     sigma_t=1)
+    # 190 is not a power of two: the geometry query validates sizes, so compare via a
+    # 256-grid with the same physical extents instead of the check-gated call
+    if nlos.nlos_rsd_check(d) == nlos.NLOS_ERR_UNSUPPORTED:
+        geom = orsd.radial_geometry(n, n, dx, dx, inp["lambda_min_m"], inp["sigma_s"])
+        assert geom.n_r == exp["n_r"] and geom.n_rho == exp["n_rho"]
+        d2 = nlos.RsdDesc(256, 256, nt, dx * n / 256, dx * n / 256, bin_ps, 1, [k], [1.0], 4, 0.5,
+                          0.1, sigma_s=1, sigma_t=1)
+        h = nlos.nlos_rsd_geometry_get(d2)
+        # same aperture, finer grid: r_max unchanged, rho_max scaled by 256/190
+        assert abs(h["r_max"] - geom.r_max) < 1e-12
+        assert h["n_r_min"] == exp["n_r_min"] and h["n_r"] == exp["n_r"]
+        assert round(h["rho_max"] * n / 256, 2) == exp["rho_max_per_m"]
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4"])
+def test_rsd_geometry_matches_oracle(name):
+    cfg = scenes.CONFIGS[name]
+    d, p = _rsd_desc(cfg)
+    h = nlos.nlos_rsd_geometry_get(d)
+    kap = orsd.wavenumbers(p.freq_bins, cfg.nt, cfg.c_dt)
+    o = orsd.radial_geometry(2 * cfg.nx, 2 * cfg.ny, cfg.dx, cfg.dy, 2 * np.pi / kap.max(), 2)
+    for k in ("n_r_min", "n_r", "n_rho_min", "n_rho", "cut_idx", "last_base"):
+        assert h[k] == getattr(o, k), k
+    for k in ("r_max", "rho_max", "dr", "rho_cut", "rho_cut_bin"):
+        assert abs(h[k] - getattr(o, k)) <= 1e-12 * abs(getattr(o, k)), k
+    assert abs(h["lambda_min"] - o.lam_min) <= 1e-12 * o.lam_min
+
+
+@pytest.mark.parametrize("name,nd", [("c1", 64), ("c2", 8)])
+def test_rsd_host_kernel_matches_oracle(name, nd):
+    cfg = scenes.CONFIGS[name]
+    d, p = _rsd_desc(cfg, n_depth=nd)
+    K = nlos.nlos_rsd_kernel_host(d)
+    depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
+    st = orsd.setup(cfg.ny, cfg.nx, cfg.nt, cfg.dx, cfg.dy, cfg.c_dt, 2, p.freq_bins, depths)
+    ref = st.K
+    assert K.shape == ref.shape
+    err = np.abs(K.astype(np.complex128) - ref).max() / np.abs(ref).max()
+    assert err < 2e-7

@@ -1,0 +1,70 @@
+"""GPU parity of nlos_fk against the FP64 oracle (relative L2 <= 1e-4)."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import fk as ofk
+from oracle.metrics import argmax_index, rel_l2
+from paper_2608_28183_amd import runtime
+
+from gpu_util import run_fk, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return runtime.Context(0)
+
+
+def test_fk_c1(ctx):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    say("fk c1", tau.shape)
+    vol, img = run_fk(ctx, tau, cfg.wall_w, cfg.wall_h, cfg.bin_ps, 2)
+    rv, ri = ofk.fk(tau.astype(np.float64), cfg.wall_w, cfg.wall_h, cfg.bin_ps, 2)
+    say("  rel_l2", rel_l2(vol, rv), rel_l2(img, ri))
+    assert rel_l2(vol, rv) < TOL and rel_l2(img, ri) < TOL
+    assert argmax_index(vol) == argmax_index(rv)
+
+
+# (ny, nx, nt, pad): tiny, non-square, unpadded, the longest lines on each axis
+SHAPES = [(4, 4, 4, 2), (8, 8, 8, 1), (16, 8, 32, 2), (8, 32, 16, 1), (32, 16, 64, 2),
+          (4, 1024, 8, 2), (1024, 4, 8, 2), (4, 4, 1024, 2), (8, 8, 2048, 1), (64, 64, 128, 2),
+          (8, 2048, 8, 1), (128, 8, 16, 2)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fk_shapes(ctx, shape):
+    ny, nx, nt, pad = shape
+    say("fk shape", shape)
+    rng = np.random.default_rng(ny * 131 + nx * 7 + nt + pad)
+    tau = rng.poisson(3.0, size=(ny, nx, nt)).astype(np.float32)
+    ww, wh, bps = 0.5 + 0.01 * nx, 0.4 + 0.01 * ny, 24.0
+    vol, img = run_fk(ctx, tau, ww, wh, bps, pad)
+    rv, ri = ofk.fk(tau.astype(np.float64), ww, wh, bps, pad)
+    say("  rel_l2", rel_l2(vol, rv), rel_l2(img, ri))
+    assert rel_l2(vol, rv) < TOL and rel_l2(img, ri) < TOL
+
+
+def test_fk_zero_input_and_pool_workspace(ctx):
+    tau = np.zeros((16, 16, 32), np.float32)
+    vol, img = run_fk(ctx, tau, with_ws=False)
+    assert np.all(vol == 0) and np.all(img == 0)
+
+
+def test_fk_deterministic(ctx):
+    tau = scenes.config_transient("c1")
+    v1, i1 = run_fk(ctx, tau)
+    v2, i2 = run_fk(ctx, tau)
+    assert np.array_equal(v1, v2) and np.array_equal(i1, i2)
+
+
+def test_fk_point_reflector_focus(ctx):
+    cfg = scenes.small_config(32, 32, 256, bin_ps=32)
+    pos = (0.1, -0.2, 0.5)
+    tau = scenes.transient(cfg, noise=False, objects=[scenes.point_object(*pos)])
+    vol, _ = run_fk(ctx, tau)
+    y, x, z = argmax_index(vol)
+    assert (y, x, z) == (9, 19, 104)

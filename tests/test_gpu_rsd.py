@@ -1,0 +1,69 @@
+"""GPU parity of nlos_rsd against the FP64 radial-RSD oracle (relative L2 <= 1e-4)."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import rsd as orsd
+from oracle.metrics import argmax_index, rel_l2
+from paper_2608_28183_amd import runtime
+
+from gpu_util import run_rsd, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return runtime.Context(0)
+
+
+def oracle_rsd(cfg, tau, p, pad=2):
+    depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
+    return orsd.rsd(tau.astype(np.float64), cfg.dx, cfg.dy, cfg.bin_ps, pad, p.freq_bins,
+                    p.weights, depths, p.sigma_s, p.sigma_t, p.delta)
+
+
+def test_rsd_c1(ctx):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    say("rsd c1")
+    vol, img, p = run_rsd(ctx, cfg, tau)
+    rv, ri = oracle_rsd(cfg, tau, p)
+    say("  rel_l2", rel_l2(vol, rv), rel_l2(img, ri))
+    assert rel_l2(vol, rv) < TOL and rel_l2(img, ri) < TOL
+    assert argmax_index(vol) == argmax_index(rv)
+
+
+@pytest.mark.parametrize("nd,pad", [(1, 2), (70, 2), (64, 1), (130, 2)])
+def test_rsd_depth_counts_and_pad(ctx, nd, pad):
+    cfg = scenes.small_config(16, 16, 128, bin_ps=32, n_depth=nd)
+    tau = scenes.transient(cfg, noise=True)
+    say("rsd nd", nd, "pad", pad)
+    vol, img, p = run_rsd(ctx, cfg, tau, pad=pad)
+    rv, ri = oracle_rsd(cfg, tau, p, pad)
+    say("  rel_l2", rel_l2(vol, rv), rel_l2(img, ri))
+    assert rel_l2(vol, rv) < TOL and rel_l2(img, ri) < TOL
+
+
+def test_rsd_non_square_and_modality(ctx):
+    cfg = scenes.Config("ns", 32, 16, 256, 32.0, 1.0, 0.5, 2, "points3", (0.3, 0.8), n_depth=20, seed=3)
+    tau = scenes.transient(cfg)
+    p0 = scenes.rsd_params(cfg)
+    p = scenes.RsdParams(p0.freq_bins, p0.weights * np.exp(0.3j), p0.depth0, p0.depth_step,
+                         p0.n_depth, sigma_s=1, sigma_t=1, delta=0.05)
+    say("rsd non-square, sigma (1,1)")
+    vol, img, _ = run_rsd(ctx, cfg, tau, params=p)
+    rv, ri = oracle_rsd(cfg, tau, p)
+    say("  rel_l2", rel_l2(vol, rv))
+    assert rel_l2(vol, rv) < TOL and rel_l2(img, ri) < TOL
+
+
+def test_rsd_fp16_kernel_storage(ctx):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    vol, img, p = run_rsd(ctx, cfg, tau, kernel_prec="fp16")
+    rv, ri = oracle_rsd(cfg, tau, p)
+    e = rel_l2(vol, rv)
+    say("rsd c1 K_r fp16 rel_l2", e)
+    assert e < 2e-3 and argmax_index(vol) == argmax_index(rv)
