@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the NLOS hot path on one MI355X.
+
+Default workload: f-k migration of a 256 x 256 x 512 confocal transient
+(32 ps bins, 1 m wall, seeded scene of 5 planar patches and 3 spheres), zero
+padded to 512 x 512 x 1024, FP32, input resident in HBM.  One step is one
+complete nlos_fk call (5 kernel passes + the image clear).  Prints one JSON
+line with volumes/s, the HBM roofline of the dominant kernel and the FP64
+oracle's CPU throughput on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload fk_c4|fk_c3|rsd_c3|rsd_c2|bin_c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+F32_VALU_PEAK_TFLOPS = 157.3
+
+
+def fk_pass_bytes(ny, nx, nt, pad):
+    """Algorithmic HBM bytes of each f-k pass: every pruned intermediate written once
+    and read once as complex64; tau read as float32; vol written as float32."""
+    Mx, My = pad * nx, pad * ny
+    c = 8
+    return {
+        "fk_x": 4 * ny * nx * nt + c * ny * Mx * nt,
+        "fk_y": c * ny * Mx * nt + c * My * Mx * nt,
+        "fk_column": 2 * c * My * Mx * nt,
+        "fk_yi": c * My * Mx * nt + c * ny * Mx * nt,
+        "fk_xi": c * ny * Mx * nt + 4 * ny * nx * nt + 4 * ny * nx,
+        "fill": 4 * ny * nx,
+    }
+
+
+def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho):
+    Mx, My = pad * nx, pad * ny
+    c = 8
+    return {
+        "rsd_phasor": 4 * ny * nx * nt + c * nf * ny * nx,
+        "rsd_x": c * nf * ny * nx + c * nf * ny * Mx,
+        "rsd_y": c * nf * ny * Mx + c * nf * My * Mx,
+        # spectra, radius map, kernel rows (read at least once) and the propagated planes
+        "rsd_propagate": c * nf * My * Mx + 4 * My * Mx + c * nrho * nf * nd + c * nd * My * Mx,
+        "rsd_yi": c * nd * My * Mx + c * nd * ny * Mx,
+        "rsd_xi": c * nd * ny * Mx + 4 * nd * ny * nx + 4 * ny * nx,
+        "fill": 4 * ny * nx,
+    }
+
+
+def cpu_baseline_fk(cfg, fraction=8):
+    """The FP64 oracle, untuned, on a bounded sample of the f-k workload: each oracle
+    step runs on 1/fraction of its independent slices of the full-size padded volume
+    (random data of the same shape: the matrix-DFT cost does not depend on values),
+    and the per-volume time is the sum of the steps scaled by `fraction`."""
+    import numpy as np
+    from oracle import fk as ofk
+    from oracle.dft import dft
+    ny, nx, nt, pad = cfg.ny, cfg.nx, cfg.nt, cfg.pad
+    My, Mx, Mt = pad * ny, pad * nx, pad * nt
+    rng = np.random.default_rng(0)
+    t_total = 0.0
+    tau = rng.poisson(2.0, size=(ny // fraction, nx, nt)).astype(np.float64)
+    t = time.perf_counter(); G = ofk.scale_and_pad(tau, pad); t_total += time.perf_counter() - t
+    sub = (My // fraction, Mx, Mt)
+    X = rng.normal(size=sub) + 1j * rng.normal(size=sub)
+    for ax in (2, 1):
+        for inv in (False, True):
+            t = time.perf_counter(); dft(X, ax, inverse=inv); t_total += time.perf_counter() - t
+    suby = (My, Mx // fraction, Mt)
+    Y = rng.normal(size=suby) + 1j * rng.normal(size=suby)
+    for inv in (False, True):
+        t = time.perf_counter(); dft(Y, 0, inverse=inv); t_total += time.perf_counter() - t
+    sx, sy = ofk.stolt_constants(cfg.dx, cfg.dy, cfg.bin_ps)
+    t = time.perf_counter(); out = ofk.stolt(X, sx, sy); t_total += time.perf_counter() - t
+    t = time.perf_counter(); v = np.abs(out[:, :nx, :nt]) ** 2; v.max(axis=2); t_total += time.perf_counter() - t
+    del G, X, Y, out, v
+    return t_total * fraction, t_total
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        return max(n) if n else None
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="fk_c4",
+                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2"])
+    ap.add_argument("--prec", default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2608_28183_amd import nlos, runtime
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    kind, cname = args.workload.split("_")
+    cfg = scenes.CONFIGS[cname]
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    ctx = runtime.Context(0, stream)
+    ny, nx, nt = cfg.ny, cfg.nx, cfg.nt
+    print(f"[bench] workload {args.workload}: generating input", file=sys.stderr, flush=True)
+
+    if kind == "fk":
+        tau = torch.from_numpy(scenes.config_transient(cname)).to(dev)
+        plan = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad, args.prec)
+        ws = plan.workspace()
+        vol = torch.empty((ny, nx, nt), device=dev)
+        img = torch.empty((ny, nx), device=dev)
+        step = lambda: plan(tau, vol, img, ws)  # noqa: E731
+        pass_bytes = fk_pass_bytes(ny, nx, nt, cfg.pad)
+        metric, unit = "fk_volumes_per_s", "volumes/s"
+        units_per_step = 1
+        workload = {"workload": f"f-k migration {ny}x{nx}x{nt} padded x{cfg.pad} "
+                                f"to {cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt}",
+                    "shape": [ny, nx, nt], "pad": cfg.pad, "bin_ps": cfg.bin_ps, "wall_m": cfg.wall_w,
+                    "scene": cfg.scene, "precision": args.prec}
+    elif kind == "rsd":
+        tau = torch.from_numpy(scenes.config_transient(cname) if cname != "c2"
+                               else scenes.transient(cfg)).to(dev)
+        p = scenes.rsd_params(cfg)
+        plan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
+                               p.weights, p.n_depth, p.depth0, p.depth_step)
+        ws = plan.workspace()
+        vol = torch.empty((p.n_depth, ny, nx), device=dev)
+        img = torch.empty((ny, nx), device=dev)
+        step = lambda: plan(tau, vol, img, ws)  # noqa: E731
+        g = nlos.nlos_rsd_geometry_get(plan.desc)
+        pass_bytes = rsd_pass_bytes(ny, nx, nt, cfg.pad, len(p.freq_bins), p.n_depth, g["n_rho"])
+        metric, unit = "rsd_volumes_per_s", "volumes/s"
+        units_per_step = 1
+        workload = {"workload": f"radial RSD {ny}x{nx}x{nt} padded x{cfg.pad}, "
+                                f"{len(p.freq_bins)} freqs, {p.n_depth} depths",
+                    "shape": [ny, nx, nt], "pad": cfg.pad, "n_freq": len(p.freq_bins),
+                    "n_depth": p.n_depth}
+    else:  # bin
+        ev = scenes.config_events(cname, "shuffled")
+        d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)
+        hist = torch.empty((ny, nx, nt), dtype=torch.int32, device=dev)
+        dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+        n = len(ev)
+        step = lambda: runtime.bin_events(ctx, d_ev, n, hist, int(cfg.bin_ps), 0, False, dropped)  # noqa
+        pass_bytes = {"bin": 8 * n + 4 * ny * nx * nt, "fill": 4 * ny * nx * nt}
+        metric, unit = "events_per_s", "events/s"
+        units_per_step = n
+        workload = {"workload": f"photon binning of {n} events into {ny}x{nx}x{nt}",
+                    "n_events": n, "shape": [ny, nx, nt]}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # timed region: K back-to-back steps on one stream
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    value = units_per_step / sec
+
+    # per-pass kernel durations from HIP events on the launch stream, same K steps
+    nlos.nlos_timing_enable(ctx.handle, True)
+    for _ in range(args.steps):
+        step()
+    passes = nlos.nlos_timing_read(ctx.handle)
+    nlos.nlos_timing_enable(ctx.handle, False)
+    avg_ms = {k: v[0] / v[1] for k, v in passes.items()}
+    dom = max((k for k in avg_ms if k in pass_bytes and k != "fill"), key=lambda k: avg_ms[k])
+    achieved = pass_bytes[dom] / (avg_ms[dom] * 1e-3) / 1e9
+    traffic = None
+    prof_path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(prof_path):
+        try:
+            from paper_2608_28183_amd import build as _b
+            rec = json.load(open(prof_path)).get(f"{args.workload}:{dom}")
+            if rec and rec.get("source_sha") == _b.source_sha():
+                traffic = rec["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": pass_bytes[dom], "avg_ms": round(avg_ms[dom], 4)}
+    total_alg = sum(v for k, v in pass_bytes.items())
+    print(f"[bench] {args.steps} steps: {sec*1e3:.3f} ms/step; passes (avg ms): "
+          + ", ".join(f"{k} {v:.3f}" for k, v in avg_ms.items()), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline and kind == "fk":
+        try:
+            est, spent = cpu_baseline_fk(cfg)
+            cpu = {"value": round(1.0 / est, 6), "unit": unit, "cores": blas_threads() or
+                   len(os.sched_getaffinity(0)), "kind": "oracle",
+                   "sample": f"every FP64 oracle step on 1/8 of its independent slices of the "
+                             f"{cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt} volume, scaled x8 "
+                             f"({spent:.1f} s of CPU time measured)",
+                   "host_cpus": len(os.sched_getaffinity(0))}
+        except MemoryError:
+            cpu = None
+
+    line = {
+        "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else args.prec, "data": "synthetic",
+        "config": workload, "roofline": roofline, "cpu_baseline": cpu,
+        "passes_ms": {k: round(v, 4) for k, v in avg_ms.items()},
+        "step_frac_of_hbm": round(total_alg * value / units_per_step / (HBM_PEAK_GBS * 1e9), 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

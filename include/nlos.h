@@ -70,6 +70,35 @@ const char *nlos_last_error(const nlos_ctx *ctx);
 /* Library ABI version (major * 100 + minor). */
 int nlos_version(void);
 
+/* Per-pass timing, a profiling aid.  While enabled, every kernel launch of
+ * nlos_bin / nlos_fk / nlos_rsd on ctx is bracketed by two HIP events on the
+ * context's stream (the only cost is the two event records per launch). */
+typedef enum {
+  NLOS_PASS_FILL = 0,          /* zero fill of an output (histogram, image) */
+  NLOS_PASS_BIN = 1,           /* event binning */
+  NLOS_PASS_FK_X = 2,          /* f-k pass 1: x-FFT with time scaling and zero padding */
+  NLOS_PASS_FK_Y = 3,          /* f-k pass 2: y-FFT */
+  NLOS_PASS_FK_COLUMN = 4,     /* f-k pass 3: t-FFT, Stolt remap, z-IFFT per column */
+  NLOS_PASS_FK_YI = 5,         /* f-k pass 4: y-IFFT */
+  NLOS_PASS_FK_XI = 6,         /* f-k pass 5: x-IFFT, |.|^2, max over depth */
+  NLOS_PASS_RSD_PHASOR = 7,    /* RSD: temporal DFT to the selected frequencies */
+  NLOS_PASS_RSD_X = 8,         /* RSD: x-FFT of the padded phasor planes */
+  NLOS_PASS_RSD_Y = 9,         /* RSD: y-FFT */
+  NLOS_PASS_RSD_PROPAGATE = 10,/* RSD: radial-kernel propagation */
+  NLOS_PASS_RSD_YI = 11,       /* RSD: y-IFFT per depth */
+  NLOS_PASS_RSD_XI = 12,       /* RSD: x-IFFT, |.|, max over depth */
+  NLOS_PASS_COUNT = 13
+} nlos_pass;
+
+/* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
+nlos_status nlos_timing_enable(nlos_ctx *ctx, int enable);
+/* Waits for the context's stream, then writes, for every pass p < n (n at most
+ * NLOS_PASS_COUNT), the total milliseconds and the number of launches recorded
+ * since the previous read into ms[p] and count[p], and clears the record. */
+nlos_status nlos_timing_read(nlos_ctx *ctx, double *ms, int *count, int n);
+/* Static name of a pass ("fk_column", ...), or "?" when out of range. */
+const char *nlos_pass_name(int pass);
+
 /* ------------------------------------------------------------------------ */
 /* Photon-event binning (Section 4.1: GPU histogramming of photon records)   */
 /* ------------------------------------------------------------------------ */
@@ -98,6 +127,11 @@ nlos_status nlos_bin_check(const nlos_bin_desc *desc);
  * independent. */
 nlos_status nlos_bin(nlos_ctx *ctx, const nlos_bin_desc *desc, const nlos_event *d_events,
                      uint64_t n_events, uint32_t *d_hist, unsigned long long *d_dropped);
+
+/* Converts n binned counts (uint32, e.g. the output of nlos_bin) to float32
+ * transient samples, d_tau[i] = (float)d_hist[i], so that a binned histogram can
+ * feed nlos_fk / nlos_rsd.  Buffers may not overlap. */
+nlos_status nlos_counts_to_float(nlos_ctx *ctx, const uint32_t *d_hist, float *d_tau, uint64_t n);
 
 /* ------------------------------------------------------------------------ */
 /* f-k migration (Section 4.2; Algorithms 1-2)                               */

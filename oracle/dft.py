@@ -21,12 +21,22 @@ def dft_matrix(m: int, inverse: bool = False) -> np.ndarray:
 def dft(x: np.ndarray, axis: int, inverse: bool = False) -> np.ndarray:
     """Unnormalised forward DFT (or 1/M-normalised inverse) along ``axis``."""
     x = np.asarray(x, dtype=np.complex128)
-    m = x.shape[axis]
+    shape = x.shape
+    axis = axis % x.ndim
+    m = shape[axis]
     f = dft_matrix(m, inverse)  # symmetric: F[n, k] = F[k, n]
-    y = np.moveaxis(x, axis, -1) @ f
+    a = int(np.prod(shape[:axis], dtype=np.int64))
+    b = int(np.prod(shape[axis + 1:], dtype=np.int64))
+    xv = np.ascontiguousarray(x).reshape(a, m, b)
+    y = np.empty_like(xv)
+    if b == 1:
+        y[:, :, 0] = xv[:, :, 0] @ f
+    else:
+        for i in range(a):          # X[k, :] = sum_n F[k, n] x[n, :]
+            y[i] = f @ xv[i]
     if inverse:
         y /= m
-    return np.moveaxis(y, -1, axis)
+    return y.reshape(shape)
 
 
 def dftn(x: np.ndarray, axes, inverse: bool = False) -> np.ndarray:

@@ -65,3 +65,14 @@ def build(verbose: bool = False) -> str:
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
+
+
+def source_sha() -> str:
+    """sha256 over the kernel and host sources (identifies the built code)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()

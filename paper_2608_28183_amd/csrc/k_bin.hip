@@ -9,6 +9,21 @@ __global__ __launch_bounds__(256) void fill_u32(uint32_t* __restrict__ p, size_t
   for (; i < n; i += stride) p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void u32_to_f32(const uint32_t* __restrict__ in, float* __restrict__ out,
+                                                  size_t n) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (; i < n; i += stride) out[i] = (float)in[i];
+}
+
+hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(u32_to_f32, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 255) / 256;

@@ -32,6 +32,11 @@ bool is_pow2_in(long long n, long long lo, long long hi) {
 
 }  // namespace
 
+struct TimedLaunch {
+  int pass;
+  hipEvent_t start, stop;
+};
+
 struct nlos_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -39,6 +44,9 @@ struct nlos_ctx {
   void* pool = nullptr;       // workspace when the caller passes none
   size_t pool_bytes = 0;
   std::string err;
+  bool timing = false;
+  std::vector<TimedLaunch> recs;      // launches recorded since the last read
+  std::vector<hipEvent_t> spare;      // recycled events
 };
 
 struct nlos_fk_plan {
@@ -79,9 +87,74 @@ static nlos_status fail(nlos_ctx* ctx, nlos_status s, const char* fmt, ...) {
                   "%s: %s", #call, hipGetErrorString(e_));                                    \
   } while (0)
 
+// Runs launch() and, when timing is on, brackets it with events on the stream.
+template <class F>
+static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
+  if (!ctx->timing) return launch();
+  hipEvent_t ev[2];
+  for (auto& e : ev) {
+    if (!ctx->spare.empty()) {
+      e = ctx->spare.back();
+      ctx->spare.pop_back();
+    } else {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+  }
+  hipError_t r = hipEventRecord(ev[0], ctx->stream);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(ev[1], ctx->stream);
+  if (r != hipSuccess) {
+    ctx->spare.push_back(ev[0]);
+    ctx->spare.push_back(ev[1]);
+    return r;
+  }
+  ctx->recs.push_back({pass, ev[0], ev[1]});
+  return hipSuccess;
+}
+
+static const char* const kPassNames[NLOS_PASS_COUNT] = {
+    "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
+    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi"};
+
 extern "C" {
 
 int nlos_version(void) { return 100; }
+
+const char* nlos_pass_name(int pass) {
+  return (pass >= 0 && pass < NLOS_PASS_COUNT) ? kPassNames[pass] : "?";
+}
+
+nlos_status nlos_timing_enable(nlos_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_timing_enable: ctx is NULL");
+  ctx->timing = enable != 0;
+  return NLOS_OK;
+}
+
+nlos_status nlos_timing_read(nlos_ctx* ctx, double* ms, int* count, int n) {
+  if (!ctx || !ms || !count || n < 0 || n > NLOS_PASS_COUNT)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_timing_read: bad arguments");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int p = 0; p < n; ++p) {
+    ms[p] = 0.0;
+    count[p] = 0;
+  }
+  nlos_status st = NLOS_OK;
+  for (const TimedLaunch& t : ctx->recs) {
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, t.start, t.stop) != hipSuccess) st = NLOS_ERR_DEVICE;
+    if (t.pass < n) {
+      ms[t.pass] += e;
+      count[t.pass] += 1;
+    }
+    ctx->spare.push_back(t.start);
+    ctx->spare.push_back(t.stop);
+  }
+  ctx->recs.clear();
+  if (st != NLOS_OK) return fail(ctx, st, "nlos_timing_read: hipEventElapsedTime failed");
+  return NLOS_OK;
+}
 
 const char* nlos_status_string(nlos_status s) {
   switch (s) {
@@ -140,6 +213,11 @@ nlos_status nlos_destroy(nlos_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->pool) (void)hipFree(ctx->pool);
   if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+  for (auto& t : ctx->recs) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto& e : ctx->spare) (void)hipEventDestroy(e);
   delete ctx;
   return NLOS_OK;
 }
@@ -198,12 +276,26 @@ nlos_status nlos_bin(nlos_ctx* ctx, const nlos_bin_desc* d, const nlos_event* d_
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const size_t nbins = (size_t)d->nx * d->ny * d->nt;
   if (!d->accumulate) {
-    HIP_TRY(ctx, nlos::launch_fill_u32(d_hist, nbins, 0u, ctx->stream));
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] { return nlos::launch_fill_u32(d_hist, nbins, 0u, ctx->stream); }));
     if (d_dropped)
-      HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_dropped), 2, 0u, ctx->stream));
+      HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+        return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_dropped), 2, 0u, ctx->stream);
+      }));
   }
-  HIP_TRY(ctx, nlos::launch_bin(d_events, n_events, d_hist, d_dropped, d->nx * d->ny, d->nt, d->bin_ps,
-                                d->t0_ps, ctx->stream));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_BIN, [&] {
+    return nlos::launch_bin(d_events, n_events, d_hist, d_dropped, d->nx * d->ny, d->nt, d->bin_ps,
+                            d->t0_ps, ctx->stream);
+  }));
+  return NLOS_OK;
+}
+
+nlos_status nlos_counts_to_float(nlos_ctx* ctx, const uint32_t* d_hist, float* d_tau, uint64_t n) {
+  if (!ctx) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_counts_to_float: ctx is NULL");
+  if (n > 0 && (!d_hist || !d_tau)) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_counts_to_float: NULL buffer");
+  if (n > 0 && (const void*)d_hist < (const void*)(d_tau + n) && (const void*)d_tau < (const void*)(d_hist + n))
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_counts_to_float: buffers overlap");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] { return nlos::launch_u32_to_f32(d_hist, d_tau, n, ctx->stream); }));
   return NLOS_OK;
 }
 
@@ -288,7 +380,10 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   float2* W2 = W1 + (size_t)ny * Mx * nt;            // [My][Mx][nt]
   hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
-  if (d_img) HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s));
+  if (d_img)
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+      return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
+    }));
 
   StridedArgs a{};
   // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx
@@ -296,31 +391,31 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   a.in_plane = nx * nt; a.in_line = nt; a.out_plane = Mx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)nx; a.n_out = (int)Mx;
   a.tscale = (float)(1.0 / (double)(nt - 1));
-  HIP_TRY(ctx, nlos::launch_strided((int)Mx, false, nlos::LD_TAU_SCALED, nlos::ST_C64, a, (int)ny, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_TAU_SCALED, nlos::ST_C64, a, (int)ny, tw, s); }));
   // pass 2: y-FFT, zero padded to My
   a = StridedArgs{};
   a.in = W1; a.out = W2;
   a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
   // pass 3: per (ky, kx) column: t-FFT, Stolt + Jacobian + 1/(Mx My Mt), z-IFFT, keep z < nt
   FkColumnArgs c{};
   c.W = W2; c.ncols = My * Mx; c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
-  HIP_TRY(ctx, nlos::launch_fk_column(p->Mt, c, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column(p->Mt, c, tw, s); }));
   // pass 4: y-IFFT, keep y < ny
   a = StridedArgs{};
   a.in = W2; a.out = W1;
   a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
   // pass 5: x-IFFT, keep x < nx, |Psi|^2 and the max over depth
   a = StridedArgs{};
   a.in = W1; a.out = d_vol;
   a.in_plane = Mx * nt; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.oscale = 1.0f; a.img = d_img; a.img_plane = nx;
-  HIP_TRY(ctx, nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS2_IMG, a, (int)ny, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS2_IMG, a, (int)ny, tw, s); }));
   return NLOS_OK;
 }
 
@@ -502,38 +597,41 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
   float2* C = B + (size_t)Nf * My * Mx;                      // [Nd][My][Mx]
   hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
-  if (d_img) HIP_TRY(ctx, nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s));
+  if (d_img)
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+      return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
+    }));
 
   // 1. phasors: t-FFT of each pixel, bins k_f -> A[f][y][x] (row stride Mx)
   ContigArgs c{};
   c.in = d_tau; c.out = A; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
   c.bins = p->d_bins; c.nbins = (int)Nf; c.out_fstride = ny * Mx; c.row_in = nx; c.row_out = Mx;
-  HIP_TRY(ctx, nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
   // 2. x-FFT of the top-left padded planes, in place in A
   c = ContigArgs{};
   c.in = A; c.out = A; c.nlines = Nf * ny; c.in_line = Mx; c.out_line = Mx; c.n_in = (int)nx; c.n_out = (int)Mx;
-  HIP_TRY(ctx, nlos::launch_contig((int)Mx, false, nlos::CL_C64, nlos::CS_C64, c, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_X, [&] { return nlos::launch_contig((int)Mx, false, nlos::CL_C64, nlos::CS_C64, c, tw, s); }));
   // 3. y-FFT: A -> B[f][My][Mx]
   StridedArgs a{};
   a.in = A; a.out = B; a.in_plane = ny * Mx; a.in_line = Mx; a.out_plane = My * Mx; a.out_line = Mx;
   a.ncols = (int)Mx; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Nf, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Nf, tw, s); }));
   // 4. radial propagation: B -> C[d][My][Mx]
   nlos::RsdPropArgs r{};
   r.Ph = B; r.Kr = p->d_kr; r.rho = p->d_rho; r.w = p->d_w; r.C = C; r.npix = My * Mx;
   r.Nf = (int)Nf; r.Nd = (int)Nd; r.rho_cut_bin = (float)p->g.rho_cut_bin; r.cut_idx = p->g.cut_idx;
   r.last_base = p->g.last_base; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
-  HIP_TRY(ctx, nlos::launch_rsd_propagate(r, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
   // 5. y-IFFT, keep y < ny: C -> A[d][ny][Mx]
   a = StridedArgs{};
   a.in = C; a.out = A; a.in_plane = My * Mx; a.in_line = Mx; a.out_plane = ny * Mx; a.out_line = Mx;
   a.ncols = (int)Mx; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Nd, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Nd, tw, s); }));
   // 6. x-IFFT, keep x < nx, |I| / (Mx My) and the max over depth
   c = ContigArgs{};
   c.in = A; c.out = d_vol; c.nlines = Nd * ny; c.in_line = Mx; c.out_line = nx; c.n_in = (int)Mx;
   c.n_out = (int)nx; c.oscale = (float)(1.0 / ((double)Mx * (double)My)); c.img = d_img; c.img_lines = ny;
-  HIP_TRY(ctx, nlos::launch_contig((int)Mx, true, nlos::CL_C64, nlos::CS_ABS_IMG, c, tw, s));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_XI, [&] { return nlos::launch_contig((int)Mx, true, nlos::CL_C64, nlos::CS_ABS_IMG, c, tw, s); }));
   return NLOS_OK;
 }
 

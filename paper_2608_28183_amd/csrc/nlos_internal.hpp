@@ -74,6 +74,7 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
 hipError_t launch_fk_column(int n, const FkColumnArgs& a, const float2* tw, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
+hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
                       unsigned long long* dropped, int npix, int nt, uint32_t bin_ps, uint32_t t0,
                       hipStream_t s);

@@ -77,8 +77,13 @@ _SIGNATURES = {
     "nlos_create": (_ST, [ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
     "nlos_destroy": (_ST, [_VP]),
     "nlos_set_stream": (_ST, [_VP, _VP]),
+    "nlos_timing_enable": (_ST, [_VP, ctypes.c_int]),
+    "nlos_timing_read": (_ST, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                               ctypes.c_int]),
+    "nlos_pass_name": (ctypes.c_char_p, [ctypes.c_int]),
     "nlos_bin_check": (_ST, [ctypes.POINTER(nlos_bin_desc)]),
     "nlos_bin": (_ST, [_VP, ctypes.POINTER(nlos_bin_desc), _VP, ctypes.c_uint64, _VP, _VP]),
+    "nlos_counts_to_float": (_ST, [_VP, _VP, _VP, ctypes.c_uint64]),
     "nlos_fk_check": (_ST, [ctypes.POINTER(nlos_fk_desc)]),
     "nlos_fk_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(ctypes.c_size_t)]),
     "nlos_fk_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(_VP)]),
@@ -165,6 +170,25 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
+NLOS_PASS_COUNT = 13
+
+
+def nlos_pass_name(p: int) -> str:
+    return lib().nlos_pass_name(p).decode()
+
+
+def nlos_timing_enable(ctx: int, enable: bool) -> None:
+    _check(lib().nlos_timing_enable(ctx, int(enable)), "nlos_timing_enable", ctx)
+
+
+def nlos_timing_read(ctx: int) -> dict:
+    """{pass name: (total ms, launches)} recorded since the previous read."""
+    ms = (ctypes.c_double * NLOS_PASS_COUNT)()
+    cnt = (ctypes.c_int * NLOS_PASS_COUNT)()
+    _check(lib().nlos_timing_read(ctx, ms, cnt, NLOS_PASS_COUNT), "nlos_timing_read", ctx)
+    return {nlos_pass_name(p): (ms[p], cnt[p]) for p in range(NLOS_PASS_COUNT) if cnt[p]}
+
+
 # ---------------------------------------------------------------------------
 # binning
 # ---------------------------------------------------------------------------
@@ -183,6 +207,13 @@ def nlos_bin(ctx: int, desc: nlos_bin_desc, events, n_events: int, hist, dropped
     hist: int32 tensor [ny, nx, nt] (uint32 counts); dropped: int64 tensor [1] or None."""
     _check(lib().nlos_bin(ctx, ctypes.byref(desc), _ptr(events), n_events, _ptr(hist),
                           _ptr(dropped)), "nlos_bin", ctx)
+
+
+def nlos_counts_to_float(ctx: int, hist, tau) -> None:
+    """tau (float32) = hist (uint32 counts held in an int32 tensor), elementwise."""
+    assert hist.numel() == tau.numel()
+    _check(lib().nlos_counts_to_float(ctx, _ptr(hist), _ptr(tau), hist.numel()),
+           "nlos_counts_to_float", ctx)
 
 
 # ---------------------------------------------------------------------------

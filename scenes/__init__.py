@@ -138,7 +138,10 @@ def _sphere(rng, depth_range, n_pts, albedo_range) -> SceneObject:
     cos_pol = k / n_pts               # in (0, 1): angle from the -z axis
     sin_pol = np.sqrt(1.0 - cos_pol ** 2)
     az = math.pi * (1.0 + 5.0 ** 0.5) * k
-    normal = np.stack([sin_pol * np.cos(az), sin_pol * np.sin(az), -cos_pol], axis=1)
+    # scalar libm trig so that the samples do not depend on the host's SIMD dispatch
+    ca = np.array([math.cos(x) for x in az])
+    sa = np.array([math.sin(x) for x in az])
+    normal = np.stack([sin_pol * ca, sin_pol * sa, -cos_pol], axis=1)
     pos = np.array([cx, cy, cz]) + rad * normal
     weight = np.full(n_pts, a * 2.0 * math.pi * rad * rad / n_pts)
     return SceneObject("sphere", pos, normal, weight)
@@ -418,7 +421,7 @@ def request_stream(n: int, rate_hz: float, seed: int = 5005,
 # on-disk cache for the slow, large inputs (plain .npy, no pickle)
 # ---------------------------------------------------------------------------
 
-GENERATOR_VERSION = 1
+GENERATOR_VERSION = 2
 
 
 def _cache_path(tag: str) -> str:
@@ -448,6 +451,12 @@ def config_transient(name: str) -> np.ndarray:
     """The seeded transient of a named config (c1, c3, c4), cached on disk."""
     cfg = CONFIGS[name]
     return cached(f"{name}_tau_{cfg.seed}", lambda: transient(cfg))
+
+
+def checksum(a: np.ndarray) -> str:
+    """sha256 of an array's bytes (identifies a generated input)."""
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
 def config_events(name: str = "c2", order: str = "shuffled") -> np.ndarray:
