@@ -5,10 +5,14 @@ import numpy as np
 
 
 def rel_l2(x, ref) -> float:
+    """||x - ref|| / ||ref||; an all-zero reference is only matched by an all-zero x."""
     x = np.asarray(x, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     n = np.linalg.norm(ref.ravel())
-    return float(np.linalg.norm((x - ref).ravel()) / (n if n > 0 else 1.0))
+    d = np.linalg.norm((x - ref).ravel())
+    if n == 0:
+        return 0.0 if d == 0 else float("inf")
+    return float(d / n)
 
 
 def max_rel(x, ref) -> float:

@@ -19,6 +19,7 @@ def ctx(lib):
 
 
 def oracle_rsd(cfg, tau, p, pad=2):
+    assert tau.sum() > 0, "empty test input"
     depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
     return orsd.rsd(tau.astype(np.float64), cfg.dx, cfg.dy, cfg.bin_ps, pad, p.freq_bins,
                     p.weights, depths, p.sigma_s, p.sigma_t, p.delta)
@@ -37,7 +38,7 @@ def test_rsd_c1(ctx):
 
 @pytest.mark.parametrize("nd,pad", [(1, 2), (70, 2), (64, 1), (130, 2)])
 def test_rsd_depth_counts_and_pad(ctx, nd, pad):
-    cfg = scenes.small_config(16, 16, 128, bin_ps=32, n_depth=nd)
+    cfg = scenes.small_config(16, 16, 128, bin_ps=64, n_depth=nd)
     tau = scenes.transient(cfg, noise=True)
     say("rsd nd", nd, "pad", pad)
     vol, img, p = run_rsd(ctx, cfg, tau, pad=pad)
