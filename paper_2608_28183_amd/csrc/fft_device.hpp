@@ -165,29 +165,24 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 // ---------------------------------------------------------------------------
-// radix plans per line length
+// radix plans: N = R0 * R1 * R2, each radix divides E (samples per thread)
 // ---------------------------------------------------------------------------
 
-template <int N>
-struct Radix;  // R0 * R1 * R2 = N, E = samples per thread, P = threads per line
-template <> struct Radix<8>    { static constexpr int R0 = 8,  R1 = 1,  R2 = 1, E = 8;  };
-template <> struct Radix<16>   { static constexpr int R0 = 16, R1 = 1,  R2 = 1, E = 16; };
-template <> struct Radix<32>   { static constexpr int R0 = 8,  R1 = 4,  R2 = 1, E = 8;  };
-template <> struct Radix<64>   { static constexpr int R0 = 8,  R1 = 8,  R2 = 1, E = 8;  };
-template <> struct Radix<128>  { static constexpr int R0 = 16, R1 = 8,  R2 = 1, E = 16; };
-template <> struct Radix<256>  { static constexpr int R0 = 16, R1 = 16, R2 = 1, E = 16; };
-template <> struct Radix<512>  { static constexpr int R0 = 16, R1 = 32, R2 = 1, E = 32; };
-template <> struct Radix<1024> { static constexpr int R0 = 32, R1 = 32, R2 = 1, E = 32; };
-template <> struct Radix<2048> { static constexpr int R0 = 32, R1 = 8,  R2 = 8, E = 32; };
+// default samples per thread for a line length
+constexpr int default_e(int n) {
+  return n <= 16 ? n : (n == 32 || n == 64) ? 8 : (n <= 256) ? 16 : 32;
+}
 
-template <int N>
+template <int N, int E_ = default_e(N)>
 struct FftShape {
-  static constexpr int R0 = Radix<N>::R0, R1 = Radix<N>::R1, R2 = Radix<N>::R2;
-  static constexpr int E = Radix<N>::E;
+  static constexpr int E = E_ < N ? E_ : N;
+  static constexpr int R0 = E;
+  static constexpr int R1 = (N / R0) < E ? (N / R0) : E;
+  static constexpr int R2 = N / (R0 * R1);
   static constexpr int P = N / E;
   static constexpr int NSTAGE = (R1 == 1) ? 1 : (R2 == 1 ? 2 : 3);
   static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
-  static_assert(E % R0 == 0 && E % R1 == 0 && E % R2 == 0, "radix must divide E");
+  static_assert(E % R1 == 0 && E % R2 == 0 && R2 <= E, "radix must divide E");
 };
 
 // Element indices touched by thread p in a stage of radix R:
@@ -220,6 +215,59 @@ __device__ __forceinline__ void stage_compute(float2* v, int p, const float2* __
         v[b * R + r] = cmul(v[b * R + r], w);
       });
     }
+    dft<R, INV>(v + b * R);
+  });
+}
+
+// Inter-stage twiddles of thread p kept in registers (loaded once, reused for
+// every line the thread transforms): stage 1 (span R0, radix R1) and stage 2
+// (span R0 R1, radix R2); entry b * (R - 1) + r - 1 is W_{Ns R}^{((p + b P) mod Ns) r}.
+template <class S>
+struct TwRegs {
+  static constexpr int N = S::R0 * S::R1 * S::R2;
+  static constexpr int E = S::E, P = S::P;
+  static constexpr int C1 = S::NSTAGE >= 2 ? (E / S::R1) * (S::R1 - 1) : 0;
+  static constexpr int C2 = S::NSTAGE >= 3 ? (E / S::R2) * (S::R2 - 1) : 0;
+  float2 w1[C1 > 0 ? C1 : 1];
+  float2 w2[C2 > 0 ? C2 : 1];
+
+  __device__ __forceinline__ void load(int p, const float2* __restrict__ tw) {
+    if constexpr (C1 > 0) {
+      constexpr int R = S::R1, Ns = S::R0, step = kTwiddleN / (Ns * R);
+      static_for<E / R>([&](auto b_) {
+        constexpr int b = decltype(b_)::value;
+        const int jm = (p + b * P) % Ns;
+        static_for<R - 1>([&](auto r_) {
+          constexpr int r = decltype(r_)::value + 1;
+          w1[b * (R - 1) + r - 1] = tw[jm * r * step];
+        });
+      });
+    }
+    if constexpr (C2 > 0) {
+      constexpr int R = S::R2, Ns = S::R0 * S::R1, step = kTwiddleN / (Ns * R);
+      static_for<E / R>([&](auto b_) {
+        constexpr int b = decltype(b_)::value;
+        const int jm = (p + b * P) % Ns;
+        static_for<R - 1>([&](auto r_) {
+          constexpr int r = decltype(r_)::value + 1;
+          w2[b * (R - 1) + r - 1] = tw[jm * r * step];
+        });
+      });
+    }
+  }
+};
+
+// Stage with twiddles from registers w[b * (R - 1) + r - 1].
+template <int R, int E, bool INV>
+__device__ __forceinline__ void stage_compute_reg(float2* v, const float2* w) {
+  static_for<E / R>([&](auto b_) {
+    constexpr int b = decltype(b_)::value;
+    static_for<R - 1>([&](auto r_) {
+      constexpr int r = decltype(r_)::value + 1;
+      float2 t = w[b * (R - 1) + r - 1];
+      if (INV) t.y = -t.y;
+      v[b * R + r] = cmul(v[b * R + r], t);
+    });
     dft<R, INV>(v + b * R);
   });
 }

@@ -18,7 +18,8 @@
 #include "rsd_host.hpp"
 
 using nlos::ContigArgs;
-using nlos::FkColumnArgs;
+using nlos::FkPairArgs;
+using nlos::FkXArgs;
 using nlos::StridedArgs;
 
 namespace {
@@ -28,6 +29,29 @@ thread_local std::string g_err;  // failures without a context
 
 bool is_pow2_in(long long n, long long lo, long long hi) {
   return n >= lo && n <= hi && (n & (n - 1)) == 0;
+}
+
+// Elements between consecutive y (or ky) rows of the f-k intermediates: Mx * nt plus
+// 256 bytes, so that the y passes, which step through rows, do not hit the same
+// memory channels at a power-of-two stride.
+size_t fk_row_stride(size_t Mx, size_t nt) { return Mx * nt + 32; }
+
+// f-k workspace (complex elements): region A holds W1 [ny][Mx/2+1][nt] and W2
+// [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [ny][Mx][nt] (rs_full);
+// region B holds W3 [My][Mx][nt] (rs_full).
+struct FkLayout {
+  size_t rs_half, rs_full, w2_off, b_off, total;
+};
+FkLayout fk_layout(const nlos_fk_desc* d) {
+  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny, nt = d->nt, ny = d->ny;
+  FkLayout L;
+  L.rs_half = fk_row_stride(Mx / 2 + 1, nt);
+  L.rs_full = fk_row_stride(Mx, nt);
+  L.w2_off = ny * L.rs_half;
+  const size_t a = std::max((ny + My) * L.rs_half, ny * L.rs_full);
+  L.b_off = (a + 31) / 32 * 32;
+  L.total = L.b_off + My * L.rs_full;
+  return L;
 }
 
 }  // namespace
@@ -329,9 +353,7 @@ nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
   nlos_status st = nlos_fk_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bytes is NULL");
-  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny, nt = d->nt;
-  // W1 [ny][Mx][nt] + W2 [My][Mx][nt], complex float
-  *bytes = (size_t)d->ny * Mx * nt * 8 + My * Mx * nt * 8;
+  *bytes = fk_layout(d).total * 8;
   return NLOS_OK;
 }
 
@@ -365,6 +387,8 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
                     void* d_ws, size_t ws_bytes) {
   if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: ctx or plan is NULL");
   if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau is NULL");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau must be 8-byte aligned");
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: plan of another device");
   const nlos_fk_desc& d = p->d;
@@ -376,8 +400,13 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
   if (st != NLOS_OK) return st;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
-  float2* W1 = static_cast<float2*>(ws);             // [ny][Mx][nt]
-  float2* W2 = W1 + (size_t)ny * Mx * nt;            // [My][Mx][nt]
+  const FkLayout L = fk_layout(&d);
+  float2* base = static_cast<float2*>(ws);
+  float2* W1 = base;               // [ny][Mx/2+1][nt] half spectrum after the x pass
+  float2* W2 = base + L.w2_off;    // [My][Mx/2+1][nt] half spectrum after the y pass
+  float2* W3 = base + L.b_off;     // [My][Mx][nt] after the column pass
+  float2* W4 = base;               // [ny][Mx][nt] after the y-IFFT (W1, W2 are dead by then)
+  const long long RH = (long long)L.rs_half, RF = (long long)L.rs_full;
   hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
   if (d_img)
@@ -385,34 +414,35 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
+  // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx, kx in [0, Mx/2]
+  FkXArgs x{};
+  x.tau = d_tau; x.out = W1; x.out_plane = RH; x.nx = (int)nx; x.nt = (int)nt;
+  x.tscale = (float)(1.0 / (double)(nt - 1));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s); }));
+  // pass 2: y-FFT of the Mx/2 + 1 planes, zero padded to My
   StridedArgs a{};
-  // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx
-  a.in = d_tau; a.out = W1;
-  a.in_plane = nx * nt; a.in_line = nt; a.out_plane = Mx * nt; a.out_line = nt;
-  a.ncols = (int)nt; a.n_in = (int)nx; a.n_out = (int)Mx;
-  a.tscale = (float)(1.0 / (double)(nt - 1));
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_TAU_SCALED, nlos::ST_C64, a, (int)ny, tw, s); }));
-  // pass 2: y-FFT, zero padded to My
-  a = StridedArgs{};
   a.in = W1; a.out = W2;
-  a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
+  a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
-  // pass 3: per (ky, kx) column: t-FFT, Stolt + Jacobian + 1/(Mx My Mt), z-IFFT, keep z < nt
-  FkColumnArgs c{};
-  c.W = W2; c.ncols = My * Mx; c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s); }));
+  // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
+  // column and its mirror, two z-IFFTs, keep z < nt
+  FkPairArgs c{};
+  c.in = W2; c.out = W3; c.in_row = RH; c.out_row = RF;
+  c.nwork = (Mx / 2 - 1) * My + 2 * (My / 2 + 1);
+  c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column(p->Mt, c, tw, s); }));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s); }));
   // pass 4: y-IFFT, keep y < ny
   a = StridedArgs{};
-  a.in = W2; a.out = W1;
-  a.in_plane = nt; a.in_line = Mx * nt; a.out_plane = nt; a.out_line = Mx * nt;
+  a.in = W3; a.out = W4;
+  a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
   // pass 5: x-IFFT, keep x < nx, |Psi|^2 and the max over depth
   a = StridedArgs{};
-  a.in = W1; a.out = d_vol;
-  a.in_plane = Mx * nt; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
+  a.in = W4; a.out = d_vol;
+  a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.oscale = 1.0f; a.img = d_img; a.img_plane = nx;
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS2_IMG, a, (int)ny, tw, s); }));

@@ -45,10 +45,22 @@ struct ContigArgs {
   long long row_in, row_out;
 };
 
-// f-k column pass over W[ncols][nt] (column = ky * Mx + kx), in place.
-struct FkColumnArgs {
-  float2* W;
-  long long ncols;
+// f-k pass 1: tau[ny][nx][nt] (float) -> half spectrum out[ny][Mx/2 + 1][nt] with
+// plane (y) stride out_plane, two real t-columns per complex line.
+struct FkXArgs {
+  const float* tau;
+  float2* out;
+  long long out_plane;
+  int nx, nt;
+  float tscale;        // 1 / (nt - 1)
+};
+
+// f-k pass 3: input half spectrum in[ky][kx <= Mx/2][nt] (row stride in_row), output full
+// spectrum columns out[ky][kx][nt] (row stride out_row); nwork paired work items.
+struct FkPairArgs {
+  const float2* in;
+  float2* out;
+  long long in_row, out_row, nwork;
   int nt, Mx, My;
   double sxk, syk;     // Stolt coordinate per signed kx, ky in units of the t bins
   float norm;          // 1 / (Mx My Mt)
@@ -71,7 +83,8 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
                           const float2* tw, hipStream_t s);
 hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a,
                          const float2* tw, hipStream_t s);
-hipError_t launch_fk_column(int n, const FkColumnArgs& a, const float2* tw, hipStream_t s);
+hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s);
+hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s);
