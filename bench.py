@@ -27,9 +27,10 @@ F32_VALU_PEAK_TFLOPS = 157.3
 
 
 def fk_pass_bytes(ny, nx, nt, pad):
-    """Algorithmic HBM bytes of each f-k pass of the Hermitian schedule: every pruned
-    intermediate written once and read once as complex64 (half spectra kx <= Mx/2 up to
-    the column pass), tau read as float32, vol written as float32."""
+    """Algorithmic HBM bytes of each f-k pass of the schedule: every pruned intermediate
+    written once and read once as complex64 (half spectra kx <= Mx/2 up to the column
+    pass, the z-IFFT last on the cropped ny x nx columns), tau read and vol written as
+    float32."""
     Mx, My = pad * nx, pad * ny
     Mh = Mx // 2 + 1
     nwork = (Mx // 2 - 1) * My + 2 * (My // 2 + 1)
@@ -39,7 +40,8 @@ def fk_pass_bytes(ny, nx, nt, pad):
         "fk_y": c * ny * Mh * nt + c * My * Mh * nt,
         "fk_column": c * nwork * nt + c * My * Mx * nt,
         "fk_yi": c * My * Mx * nt + c * ny * Mx * nt,
-        "fk_xi": c * ny * Mx * nt + 4 * ny * nx * nt + 4 * ny * nx,
+        "fk_xi": c * ny * Mx * nt + c * ny * nx * nt,
+        "fk_zi": c * ny * nx * nt + 4 * ny * nx * nt + 4 * ny * nx,
         "fill": 4 * ny * nx,
     }
 

@@ -78,16 +78,17 @@ typedef enum {
   NLOS_PASS_BIN = 1,           /* event binning */
   NLOS_PASS_FK_X = 2,          /* f-k pass 1: x-FFT with time scaling and zero padding */
   NLOS_PASS_FK_Y = 3,          /* f-k pass 2: y-FFT */
-  NLOS_PASS_FK_COLUMN = 4,     /* f-k pass 3: t-FFT, Stolt remap, z-IFFT per column */
+  NLOS_PASS_FK_COLUMN = 4,     /* f-k pass 3: t-FFT and Stolt remap per column */
   NLOS_PASS_FK_YI = 5,         /* f-k pass 4: y-IFFT */
-  NLOS_PASS_FK_XI = 6,         /* f-k pass 5: x-IFFT, |.|^2, max over depth */
+  NLOS_PASS_FK_XI = 6,         /* f-k pass 5: x-IFFT */
   NLOS_PASS_RSD_PHASOR = 7,    /* RSD: temporal DFT to the selected frequencies */
   NLOS_PASS_RSD_X = 8,         /* RSD: x-FFT of the padded phasor planes */
   NLOS_PASS_RSD_Y = 9,         /* RSD: y-FFT */
   NLOS_PASS_RSD_PROPAGATE = 10,/* RSD: radial-kernel propagation */
   NLOS_PASS_RSD_YI = 11,       /* RSD: y-IFFT per depth */
   NLOS_PASS_RSD_XI = 12,       /* RSD: x-IFFT, |.|, max over depth */
-  NLOS_PASS_COUNT = 13
+  NLOS_PASS_FK_ZI = 13,        /* f-k pass 6: z-IFFT, |.|^2, max over depth */
+  NLOS_PASS_COUNT = 14
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */

@@ -121,6 +121,23 @@ __global__ __launch_bounds__(ContigCfg<N>::THREADS) void contig_fft(ContigArgs a
             lds[ll * C::LSTRIDE + swz(bin)];
       }
     }
+  } else if constexpr (ST == CS_ABS2_MAX) {
+    // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]
+    float m = 0.f;
+    auto store = [&](int n, float2 val) {
+      if (!lineok || n >= a.n_out) return;
+      const float e = (val.x * val.x + val.y * val.y) * a.oscale;
+      if (a.out != nullptr) static_cast<float*>(a.out)[line * a.out_line + n] = e;
+      m = fmaxf(m, e);
+    };
+    fft_run<S, INV, false>(v, p, my, idx, tw, store);
+    if (a.img != nullptr) {
+      constexpr int W = P < 64 ? P : 64;
+#pragma unroll
+      for (int off = 1; off < W; off <<= 1) m = fmaxf(m, __shfl_xor(m, off, W));
+      if (lineok && (p % W) == 0)
+        atomicMax(reinterpret_cast<unsigned int*>(a.img) + line, __float_as_uint(m));
+    }
   } else {
     auto store = [&](int n, float2 val) {
       if (!lineok || n >= a.n_out) return;
@@ -143,16 +160,16 @@ __global__ __launch_bounds__(ContigCfg<N>::THREADS) void contig_fft(ContigArgs a
 // ---------------------------------------------------------------------------
 
 // (samples per thread, columns per block) of the strided passes, from timing sweeps at
-// 512-point lines: y passes E=16 T=16, x passes (float in or out) E=16 T=32
-template <int N, int LD, int ST>
+// 512-point lines (256x256x512 f-k): forward y pass E=16 T=16, inverse passes E=8 T=16;
+// 256-point lines use 32 columns (256-byte rows)
+template <int N, bool INV, int LD, int ST>
 struct StridedTune {
-  static constexpr bool X = (LD == LD_TAU_SCALED) || (ST == ST_ABS2_IMG);
-  static constexpr int E = (N == 512) ? 16 : default_e(N);
-  static constexpr int T = (N == 512) ? (X ? 32 : 16) : (N == 256 ? 32 : default_t(N));
+  static constexpr int E = (N == 512) ? (INV ? 8 : 16) : default_e(N);
+  static constexpr int T = (N == 512) ? 16 : (N == 256 ? 32 : default_t(N));
 };
 
-template <int N, bool INV, int LD, int ST, int E = StridedTune<N, LD, ST>::E,
-          int T = StridedTune<N, LD, ST>::T>
+template <int N, bool INV, int LD, int ST, int E = StridedTune<N, INV, LD, ST>::E,
+          int T = StridedTune<N, INV, LD, ST>::T>
 static hipError_t launch_strided_n(const StridedArgs& a, int nplanes, const float2* tw,
                                    hipStream_t s) {
   using C = StridedCfg<N, E, T>;
@@ -223,6 +240,8 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
     return launch_contig_inv<false, CL_C64, CS_C64>(n, a, tw, s);
   if (inverse && ld == CL_C64 && st == CS_ABS_IMG)
     return launch_contig_inv<true, CL_C64, CS_ABS_IMG>(n, a, tw, s);
+  if (inverse && ld == CL_C64 && st == CS_ABS2_MAX)
+    return launch_contig_inv<true, CL_C64, CS_ABS2_MAX>(n, a, tw, s);
   return hipErrorInvalidValue;
 }
 

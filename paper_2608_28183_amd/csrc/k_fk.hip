@@ -9,7 +9,11 @@
 //                  serves the Stolt remap of output column (kx, ky) (w >= 0 half of
 //                  the column) and of its mirror (-kx, -ky) (conjugated w <= 0 half);
 //                  both share the Stolt coordinates, since sqrt(sx^2 X^2 + sy^2 Y^2 + Z^2)
-//                  depends on X^2 and Y^2 only.  Two inverse z-FFTs per input column.
+//                  depends on X^2 and Y^2 only.  The remapped columns (kz in [0, Mt/2),
+//                  the only non-zero half) are written out; the inverse transform along z
+//                  runs last, after the y and x inverse passes have cropped the volume to
+//                  ny x nx columns (the inverse 3D DFT is separable, so its axis order is
+//                  free), which needs a quarter of the z transforms.
 #include "fft_block.hpp"
 #include "nlos_internal.hpp"
 
@@ -168,16 +172,19 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
         vb[b * S::R0 + r] = xb;
       });
     });
-    __syncthreads();
+    // remapped columns, kz in [0, nt) (kz >= Mt/2 and kz = 0 are zero)
     float2* dst = a.out + (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
-    fft_run<S, true, false>(v, p, my, idx, tw, [&](int n, float2 val) {
-      if (ok && n < a.nt) dst[n] = val;
-    });
-    __syncthreads();
     float2* dst2 = a.out + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt;
     const bool ok2 = ok && it.has_mirror;
-    fft_run<S, true, false>(vb, p, my, idx, tw, [&](int n, float2 val) {
-      if (ok2 && n < a.nt) dst2[n] = val;
+    static_for<E / S::R0>([&](auto b_) {
+      static_for<S::R0>([&](auto r_) {
+        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+        const int kz = stage_in_index<N, S::R0, E>(p, b, r);
+        if (kz < a.nt) {
+          if (ok) dst[kz] = v[b * S::R0 + r];
+          if (ok2) dst2[kz] = vb[b * S::R0 + r];
+        }
+      });
     });
   }
 }
@@ -186,10 +193,11 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
 // launchers
 // ---------------------------------------------------------------------------
 
-// samples per thread and real-column pairs per block of the x pass
+// samples per thread and real-column pairs per block of the x pass (timing sweep at
+// 512-point lines: E=8, T=16)
 template <int N>
 struct XTune {
-  static constexpr int E = (N == 512) ? 16 : default_e(N);
+  static constexpr int E = (N == 512) ? 8 : default_e(N);
   static constexpr int T = (N == 512) ? 16 : (N == 256 ? 32 : default_t(N));
 };
 

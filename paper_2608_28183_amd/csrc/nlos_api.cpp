@@ -38,7 +38,7 @@ size_t fk_row_stride(size_t Mx, size_t nt) { return Mx * nt + 32; }
 
 // f-k workspace (complex elements): region A holds W1 [ny][Mx/2+1][nt] and W2
 // [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [ny][Mx][nt] (rs_full);
-// region B holds W3 [My][Mx][nt] (rs_full).
+// region B holds W3 [My][Mx][nt] (rs_full), later W5 [ny][nx][nt].
 struct FkLayout {
   size_t rs_half, rs_full, w2_off, b_off, total;
 };
@@ -139,7 +139,7 @@ static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
 
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
-    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi"};
+    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi"};
 
 extern "C" {
 
@@ -426,7 +426,7 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s); }));
   // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
-  // column and its mirror, two z-IFFTs, keep z < nt
+  // column and its mirror; the remapped spectra (kz < nt) go to W3
   FkPairArgs c{};
   c.in = W2; c.out = W3; c.in_row = RH; c.out_row = RF;
   c.nwork = (Mx / 2 - 1) * My + 2 * (My / 2 + 1);
@@ -439,13 +439,19 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
-  // pass 5: x-IFFT, keep x < nx, |Psi|^2 and the max over depth
+  // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt] (over W3, which is dead)
+  float2* W5 = W3;
   a = StridedArgs{};
-  a.in = W4; a.out = d_vol;
+  a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-  a.oscale = 1.0f; a.img = d_img; a.img_plane = nx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS2_IMG, a, (int)ny, tw, s); }));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
+  // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
+  // |Psi|^2 and the max over depth
+  ContigArgs z{};
+  z.in = W5; z.out = d_vol; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
+  z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = d_img;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s); }));
   return NLOS_OK;
 }
 

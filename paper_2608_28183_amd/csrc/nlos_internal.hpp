@@ -13,7 +13,7 @@ enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
 enum { ST_C64 = 0, ST_ABS2_IMG = 1 };
 // contig_fft load / store modes
 enum { CL_C64 = 0, CL_REAL = 1 };
-enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2 };
+enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2, CS_ABS2_MAX = 3 };
 
 // Lines along a strided axis.  Element n of line `col` in plane `plane` is at
 // in[plane * in_plane + n * in_line + col]; n < n_in are read (the rest are the
@@ -36,8 +36,9 @@ struct ContigArgs {
   void* out;
   long long nlines, in_line, out_line;
   int n_in, n_out;
-  float oscale;        // CS_ABS_IMG: output = |v| * oscale
-  float* img;          // CS_ABS_IMG: img[(ln % img_lines) * out_line + n] = max over lines
+  float oscale;        // CS_ABS_IMG: output = |v| * oscale; CS_ABS2_MAX: |v|^2 * oscale
+  float* img;          // CS_ABS_IMG: img[(ln % img_lines) * out_line + n] = max over lines;
+                       // CS_ABS2_MAX: img[ln] = max over the line
   long long img_lines;
   const int* bins;     // CS_BINS: out[f * out_fstride + y * row_out + x] = X[bins[f]],
   int nbins;           //          line ln = y * row_in + x

@@ -170,7 +170,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 13
+NLOS_PASS_COUNT = 14
 
 
 def nlos_pass_name(p: int) -> str:
