@@ -56,17 +56,18 @@ def fk_full_schedule_bytes(ny, nx, nt, pad):
         (c * ny * Mx * nt + 4 * ny * nx * nt)
 
 
-def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho):
+def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
+    """Algorithmic bytes of each RSD pass (frequency / depth contiguous layout)."""
     Mx, My = pad * nx, pad * ny
     c = 8
     return {
-        "rsd_phasor": 4 * ny * nx * nt + c * nf * ny * nx,
-        "rsd_x": c * nf * ny * nx + c * nf * ny * Mx,
-        "rsd_y": c * nf * ny * Mx + c * nf * My * Mx,
-        # spectra, radius map, kernel rows (read at least once) and the propagated planes
-        "rsd_propagate": c * nf * My * Mx + 4 * My * Mx + c * nrho * nf * nd + c * nd * My * Mx,
-        "rsd_yi": c * nd * My * Mx + c * nd * ny * Mx,
-        "rsd_xi": c * nd * ny * Mx + 4 * nd * ny * nx + 4 * ny * nx,
+        "rsd_phasor": 4 * ny * nx * nt + c * ny * nx * nf,
+        "rsd_x": c * ny * nx * nf + c * ny * Mx * nf,
+        "rsd_y": c * ny * Mx * nf + c * My * Mx * nf,
+        # spectra, kernel rows (read at least once), pixel chunks and the propagated planes
+        "rsd_propagate": c * My * Mx * nf + c * nrho * nf * nd + 52 * nchunks + c * My * Mx * nd,
+        "rsd_yi": c * My * Mx * nd + c * ny * Mx * nd,
+        "rsd_xi": c * ny * Mx * nd + 4 * ny * nx * nd + 4 * ny * nx,
         "fill": 4 * ny * nx,
     }
 
@@ -165,7 +166,7 @@ def main():
         plan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
                                p.weights, p.n_depth, p.depth0, p.depth_step)
         ws = plan.workspace()
-        vol = torch.empty((p.n_depth, ny, nx), device=dev)
+        vol = torch.empty((ny, nx, p.n_depth), device=dev)
         img = torch.empty((ny, nx), device=dev)
         step = lambda: plan(tau, vol, img, ws)  # noqa: E731
         g = nlos.nlos_rsd_geometry_get(plan.desc)

@@ -212,8 +212,9 @@ nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc *desc, nlos_rsd_geometry *
 nlos_status nlos_rsd_kernel_host(const nlos_rsd_desc *desc, float *out, size_t n_floats);
 /* Exact device workspace one nlos_rsd call needs (host only). */
 nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc *desc, size_t *bytes);
-/* Builds K_r (Eq. 4-6, FP64 on the host, stored per kernel_prec), the pixel-to-
- * radius map and the frequency tables, and uploads them to HBM. */
+/* Builds K_r (Eq. 4-6, FP64 on the host, stored per kernel_prec), the pixel lookup
+ * (radius map -> taper, interpolation bins and weights of Listing 3, pixels grouped by
+ * radial bin) and the frequency tables, and uploads them to HBM. */
 nlos_status nlos_rsd_plan_create(nlos_ctx *ctx, const nlos_rsd_desc *desc, nlos_rsd_plan **out);
 nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan *plan);
 
@@ -222,8 +223,9 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan *plan);
  *   C[d](u,v) = sum_f w_f P^[f](u,v) a(rho) lerp(K_r[., f, d], rho(u,v)) with the
  *   smoothstep taper a over the last 8 radial bins below the cutoff;
  *   I[d] = IDFT2(C[d]) normalised by 1/(Mx My).
- * Writes d_vol[n_depth][ny][nx] = |I| on the unpadded grid and d_img[ny][nx] =
- * max over depth; either may be NULL (not both).  Workspace as for nlos_fk. */
+ * Writes d_vol[ny][nx][n_depth] = |I| on the unpadded grid (depth contiguous, like
+ * the time axis of the transient) and d_img[ny][nx] = max over depth; either may be
+ * NULL (not both).  Workspace as for nlos_fk. */
 nlos_status nlos_rsd(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
                      float *d_img, void *d_ws, size_t ws_bytes);
 

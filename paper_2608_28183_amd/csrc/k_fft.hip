@@ -49,8 +49,10 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
     if constexpr (ST == ST_C64) {
       if (colok && n < a.n_out)
         static_cast<float2*>(a.out)[plane * a.out_plane + (long long)n * a.out_line + col] = val;
-    } else {  // |v|^2 (times a.oscale) plus a max over this tile's columns into img
-      float m = colok ? (val.x * val.x + val.y * val.y) * a.oscale : 0.f;
+    } else {  // |v|^2 or |v| (times a.oscale) plus a max over this tile's columns into img
+      float m = val.x * val.x + val.y * val.y;
+      if constexpr (ST == ST_ABS_IMG) m = sqrtf(m);
+      m = colok ? m * a.oscale : 0.f;
       if (a.out != nullptr && colok && n < a.n_out)
         static_cast<float*>(a.out)[plane * a.out_plane + (long long)n * a.out_line + col] = m;
       if (a.img != nullptr) {
@@ -69,10 +71,17 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
 // contiguous lines
 // ---------------------------------------------------------------------------
 
+// samples per thread of the contiguous passes: 16 at 1024-point lines (64 threads per
+// line), from the z-IFFT timing of the 256x256x512 f-k
+template <int N>
+struct ContigTune {
+  static constexpr int E = (N == 1024) ? 16 : default_e(N);
+};
+
 template <int N, bool INV, int LD, int ST>
-__global__ __launch_bounds__(ContigCfg<N>::THREADS) void contig_fft(ContigArgs a,
-                                                                     const float2* __restrict__ tw) {
-  using C = ContigCfg<N>;
+__global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void contig_fft(
+    ContigArgs a, const float2* __restrict__ tw) {
+  using C = ContigCfg<N, ContigTune<N>::E>;
   using S = typename C::S;
   constexpr int E = S::E, P = C::P;
   constexpr bool NEED_LDS = (S::NSTAGE > 1) || (ST == CS_BINS);
@@ -110,16 +119,11 @@ __global__ __launch_bounds__(ContigCfg<N>::THREADS) void contig_fft(ContigArgs a
     __syncthreads();
     const long long line0 = (long long)blockIdx.x * C::L;
     for (int k = tid; k < C::L * a.nbins; k += C::THREADS) {
-      const int ll = k % C::L;
-      const int f = k / C::L;
+      const int ll = k / a.nbins;
+      const int f = k % a.nbins;
       const long long ln = line0 + ll;
-      if (ln < a.nlines) {
-        const int bin = a.bins[f];
-        // pixel ln = y * row_in + x  ->  out[f][y][x] with row stride row_out
-        const long long y = ln / a.row_in, x = ln % a.row_in;
-        static_cast<float2*>(a.out)[(long long)f * a.out_fstride + y * a.row_out + x] =
-            lds[ll * C::LSTRIDE + swz(bin)];
-      }
+      if (ln < a.nlines)
+        static_cast<float2*>(a.out)[ln * a.nbins + f] = lds[ll * C::LSTRIDE + swz(a.bins[f])];
     }
   } else if constexpr (ST == CS_ABS2_MAX) {
     // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]
@@ -205,12 +209,14 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
     return launch_strided_inv<true, LD_C64, ST_C64>(n, a, nplanes, tw, s);
   if (inverse && ld == LD_C64 && st == ST_ABS2_IMG)
     return launch_strided_inv<true, LD_C64, ST_ABS2_IMG>(n, a, nplanes, tw, s);
+  if (inverse && ld == LD_C64 && st == ST_ABS_IMG)
+    return launch_strided_inv<true, LD_C64, ST_ABS_IMG>(n, a, nplanes, tw, s);
   return hipErrorInvalidValue;
 }
 
 template <int N, bool INV, int LD, int ST>
 static hipError_t launch_contig_n(const ContigArgs& a, const float2* tw, hipStream_t s) {
-  using C = ContigCfg<N>;
+  using C = ContigCfg<N, ContigTune<N>::E>;
   dim3 grid((unsigned)((a.nlines + C::L - 1) / C::L));
   hipLaunchKernelGGL((contig_fft<N, INV, LD, ST>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();

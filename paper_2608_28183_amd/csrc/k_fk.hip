@@ -140,39 +140,8 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
     const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
     const double ax = a.sxk * kxs, ay = a.syk * kys;
     const double A = ax * ax + ay * ay;
-    float2 vb[E];
-    static_for<E / S::R0>([&](auto b_) {
-      static_for<S::R0>([&](auto r_) {
-        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-        const int kz = stage_in_index<N, S::R0, E>(p, b, r);
-        float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
-        if (kz > 0 && kz < HALF) {
-          const double q2 = A + double(kz * kz);
-          const float qf = __builtin_amdgcn_sqrtf((float)q2);
-          const float rq = __builtin_amdgcn_rcpf(qf);
-          const double q0 = (double)qf;
-          const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
-          if (q <= double(HALF - 1)) {
-            const double fl = floor(q);
-            const int i0 = int(fl);
-            const int i1 = i0 + 1 < HALF ? i0 + 1 : HALF - 1;
-            const float fr = float(q - fl);
-            const float jac = float(kz) * rq * a.norm;
-            // column (kx, ky): samples i0, i1 of the w >= 0 half
-            const float2 s0 = my[swz(i0)], s1 = my[swz(i1)];
-            xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
-            xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
-            // mirror (-kx, -ky): conj of samples -i0, -i1 (mod N)
-            const float2 m0 = my[swz((N - i0) & (N - 1))], m1 = my[swz((N - i1) & (N - 1))];
-            xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
-            xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
-          }
-        }
-        v[b * S::R0 + r] = xa;
-        vb[b * S::R0 + r] = xb;
-      });
-    });
-    // remapped columns, kz in [0, nt) (kz >= Mt/2 and kz = 0 are zero)
+    // the remapped column and its mirror go straight to W3 (kz < nt; kz >= Mt/2 and
+    // kz = 0 are zero)
     float2* dst = a.out + (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
     float2* dst2 = a.out + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt;
     const bool ok2 = ok && it.has_mirror;
@@ -181,8 +150,31 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
         constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
         const int kz = stage_in_index<N, S::R0, E>(p, b, r);
         if (kz < a.nt) {
-          if (ok) dst[kz] = v[b * S::R0 + r];
-          if (ok2) dst2[kz] = vb[b * S::R0 + r];
+          float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
+          if (kz > 0 && kz < HALF) {
+            const double q2 = A + double(kz * kz);
+            const float qf = __builtin_amdgcn_sqrtf((float)q2);
+            const float rq = __builtin_amdgcn_rcpf(qf);
+            const double q0 = (double)qf;
+            const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
+            if (q <= double(HALF - 1)) {
+              const double fl = floor(q);
+              const int i0 = int(fl);
+              const int i1 = i0 + 1 < HALF ? i0 + 1 : HALF - 1;
+              const float fr = float(q - fl);
+              const float jac = float(kz) * rq * a.norm;
+              // column (kx, ky): samples i0, i1 of the w >= 0 half
+              const float2 s0 = my[swz(i0)], s1 = my[swz(i1)];
+              xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
+              xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
+              // mirror (-kx, -ky): conj of samples -i0, -i1 (mod N)
+              const float2 m0 = my[swz((N - i0) & (N - 1))], m1 = my[swz((N - i1) & (N - 1))];
+              xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
+              xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
+            }
+          }
+          if (ok) dst[kz] = xa;
+          if (ok2) dst2[kz] = xb;
         }
       });
     });

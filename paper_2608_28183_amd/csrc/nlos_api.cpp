@@ -87,9 +87,13 @@ struct nlos_rsd_plan {
   int Mx = 0, My = 0;
   nlos::RsdGeometry g{};
   void* d_kr = nullptr;       // [Nrho][Nf][Nd] float2 or __half2
-  float* d_rho = nullptr;     // [My][Mx]
   float2* d_w = nullptr;      // [Nf]
   int* d_bins = nullptr;      // [Nf]
+  int* d_chunk_i0 = nullptr;  // pixel chunks sharing a radial bin (rsd_build_chunks)
+  int* d_chunk_pix = nullptr;
+  float* d_chunk_wa = nullptr;
+  float* d_chunk_wb = nullptr;
+  long long nchunks = 0;
 };
 
 static nlos_status fail(nlos_ctx* ctx, nlos_status s, const char* fmt, ...) {
@@ -459,6 +463,26 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
 // RSD
 // ---------------------------------------------------------------------------
 
+// RSD workspace (complex elements), frequency / depth contiguous:
+//   A: phasors P [ny][nx][Nf], later the y-IFFT output D [ny][Mx][Nd]
+//   B: x-FFT output [ny][Mx][Nf], later the propagated spectra C [My][Mx][Nd]
+//   E: y-FFT output P^ [My][Mx][Nf]
+struct RsdLayout {
+  size_t b_off, e_off, total;
+};
+static RsdLayout rsd_layout(const nlos_rsd_desc* d) {
+  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny;
+  const size_t nf = d->n_freq, nd = d->n_depth, ny = d->ny, nx = d->nx;
+  auto up = [](size_t n) { return (n + 31) / 32 * 32; };
+  RsdLayout L;
+  const size_t a = up(std::max(ny * nx * nf, ny * Mx * nd));
+  const size_t b = up(std::max(ny * Mx * nf, My * Mx * nd));
+  L.b_off = a;
+  L.e_off = a + b;
+  L.total = a + b + My * Mx * nf;
+  return L;
+}
+
 static nlos::RsdInputs rsd_inputs(const nlos_rsd_desc* d) {
   nlos::RsdInputs in;
   in.nx = d->nx; in.ny = d->ny; in.nt = d->nt; in.pad = d->pad;
@@ -537,10 +561,7 @@ nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc* d, size_t* bytes) {
   nlos_status st = nlos_rsd_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bytes is NULL");
-  const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny;
-  const size_t nf = d->n_freq, nd = d->n_depth, ny = d->ny;
-  // A [max(Nf,Nd)][ny][Mx] + B [Nf][My][Mx] + C [Nd][My][Mx], complex float
-  *bytes = (std::max(nf, nd) * ny * Mx + nf * My * Mx + nd * My * Mx) * 8;
+  *bytes = rsd_layout(d).total * 8;
   return NLOS_OK;
 }
 
@@ -548,7 +569,10 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan* p) {
   if (!p) return NLOS_OK;
   (void)hipSetDevice(p->device);
   if (p->d_kr) (void)hipFree(p->d_kr);
-  if (p->d_rho) (void)hipFree(p->d_rho);
+  if (p->d_chunk_i0) (void)hipFree(p->d_chunk_i0);
+  if (p->d_chunk_pix) (void)hipFree(p->d_chunk_pix);
+  if (p->d_chunk_wa) (void)hipFree(p->d_chunk_wa);
+  if (p->d_chunk_wb) (void)hipFree(p->d_chunk_wb);
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_bins) (void)hipFree(p->d_bins);
   delete p;
@@ -572,8 +596,8 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
   p->g = nlos::rsd_geometry(in);
   std::vector<double> kre, kim;
   nlos::rsd_radial_kernel(in, p->g, kre, kim);
-  std::vector<float> rho;
-  nlos::rsd_radius_map(in, p->g, rho);
+  nlos::RsdChunks ch;
+  nlos::rsd_build_chunks(in, p->g, ch);
   const size_t nk = kre.size();
   auto cleanup = [&](nlos_status s, const char* what, hipError_t e) {
     nlos_rsd_plan_destroy(p);
@@ -598,9 +622,17 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
     if ((e = hipMemcpy(p->d_kr, kf.data(), nk * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
   }
-  if ((e = hipMalloc(&p->d_rho, rho.size() * sizeof(float))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "rho", e);
-  if ((e = hipMemcpy(p->d_rho, rho.data(), rho.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(NLOS_ERR_DEVICE, "rho upload", e);
+  p->nchunks = ch.count();
+  auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(dst, bytes);
+    if (r == hipSuccess) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return r;
+  };
+  if ((e = upload((void**)&p->d_chunk_i0, ch.i0.data(), ch.i0.size() * sizeof(int))) != hipSuccess ||
+      (e = upload((void**)&p->d_chunk_pix, ch.pix.data(), ch.pix.size() * sizeof(int))) != hipSuccess ||
+      (e = upload((void**)&p->d_chunk_wa, ch.wa.data(), ch.wa.size() * sizeof(float))) != hipSuccess ||
+      (e = upload((void**)&p->d_chunk_wb, ch.wb.data(), ch.wb.size() * sizeof(float))) != hipSuccess)
+    return cleanup(NLOS_ERR_DEVICE, "pixel chunks", e);
   std::vector<float2> w(d->n_freq);
   for (int f = 0; f < d->n_freq; ++f) w[f] = make_float2(d->w[2 * f], d->w[2 * f + 1]);
   if ((e = hipMalloc(&p->d_w, w.size() * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "w", e);
@@ -623,14 +655,17 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
   const nlos_rsd_desc& d = p->d;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const long long Nf = d.n_freq, Nd = d.n_depth;
-  const size_t need = ((size_t)std::max(Nf, Nd) * ny * Mx + (size_t)Nf * My * Mx + (size_t)Nd * My * Mx) * 8;
+  const RsdLayout L = rsd_layout(&d);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
   if (st != NLOS_OK) return st;
-  float2* A = static_cast<float2*>(ws);                      // [max(Nf,Nd)][ny][Mx]
-  float2* B = A + (size_t)std::max(Nf, Nd) * ny * Mx;        // [Nf][My][Mx]
-  float2* C = B + (size_t)Nf * My * Mx;                      // [Nd][My][Mx]
+  float2* base = static_cast<float2*>(ws);
+  float2* P = base;                 // [ny][nx][Nf]
+  float2* X = base + L.b_off;       // [ny][Mx][Nf]
+  float2* Ph = base + L.e_off;      // [My][Mx][Nf]
+  float2* C = base + L.b_off;       // [My][Mx][Nd]
+  float2* D = base;                 // [ny][Mx][Nd]
   hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
   if (d_img)
@@ -638,36 +673,39 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
-  // 1. phasors: t-FFT of each pixel, bins k_f -> A[f][y][x] (row stride Mx)
+  // 1. phasors: t-FFT of each pixel, bins k_f -> P[y][x][f]
   ContigArgs c{};
-  c.in = d_tau; c.out = A; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
-  c.bins = p->d_bins; c.nbins = (int)Nf; c.out_fstride = ny * Mx; c.row_in = nx; c.row_out = Mx;
+  c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
+  c.bins = p->d_bins; c.nbins = (int)Nf;
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
-  // 2. x-FFT of the top-left padded planes, in place in A
-  c = ContigArgs{};
-  c.in = A; c.out = A; c.nlines = Nf * ny; c.in_line = Mx; c.out_line = Mx; c.n_in = (int)nx; c.n_out = (int)Mx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_X, [&] { return nlos::launch_contig((int)Mx, false, nlos::CL_C64, nlos::CS_C64, c, tw, s); }));
-  // 3. y-FFT: A -> B[f][My][Mx]
+  // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
-  a.in = A; a.out = B; a.in_plane = ny * Mx; a.in_line = Mx; a.out_plane = My * Mx; a.out_line = Mx;
-  a.ncols = (int)Mx; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Nf, tw, s); }));
-  // 4. radial propagation: B -> C[d][My][Mx]
-  nlos::RsdPropArgs r{};
-  r.Ph = B; r.Kr = p->d_kr; r.rho = p->d_rho; r.w = p->d_w; r.C = C; r.npix = My * Mx;
-  r.Nf = (int)Nf; r.Nd = (int)Nd; r.rho_cut_bin = (float)p->g.rho_cut_bin; r.cut_idx = p->g.cut_idx;
-  r.last_base = p->g.last_base; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
-  // 5. y-IFFT, keep y < ny: C -> A[d][ny][Mx]
+  a.in = P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
+  a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
+  // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
   a = StridedArgs{};
-  a.in = C; a.out = A; a.in_plane = My * Mx; a.in_line = Mx; a.out_plane = ny * Mx; a.out_line = Mx;
-  a.ncols = (int)Mx; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Nd, tw, s); }));
-  // 6. x-IFFT, keep x < nx, |I| / (Mx My) and the max over depth
-  c = ContigArgs{};
-  c.in = A; c.out = d_vol; c.nlines = Nd * ny; c.in_line = Mx; c.out_line = nx; c.n_in = (int)Mx;
-  c.n_out = (int)nx; c.oscale = (float)(1.0 / ((double)Mx * (double)My)); c.img = d_img; c.img_lines = ny;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_XI, [&] { return nlos::launch_contig((int)Mx, true, nlos::CL_C64, nlos::CS_ABS_IMG, c, tw, s); }));
+  a.in = X; a.out = Ph; a.in_plane = Nf; a.in_line = Mx * Nf; a.out_plane = Nf; a.out_line = Mx * Nf;
+  a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  // 4. radial propagation over pixel chunks: P^ -> C[pix][d]
+  nlos::RsdPropArgs r{};
+  r.Ph = Ph; r.Kr = p->d_kr; r.w = p->d_w; r.C = C;
+  r.chunk_i0 = p->d_chunk_i0; r.chunk_pix = p->d_chunk_pix; r.chunk_wa = p->d_chunk_wa;
+  r.chunk_wb = p->d_chunk_wb; r.nchunks = p->nchunks;
+  r.Nf = (int)Nf; r.Nd = (int)Nd; r.cut_idx = p->g.cut_idx; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
+  // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d]
+  a = StridedArgs{};
+  a.in = C; a.out = D; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;
+  a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  // 6. x-IFFT, keep x < nx, |I| / (Mx My) -> vol[y][x][d], max over depth -> img
+  a = StridedArgs{};
+  a.in = D; a.out = d_vol; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
+  a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
+  a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s); }));
   return NLOS_OK;
 }
 

@@ -10,7 +10,7 @@ namespace nlos {
 
 // strided_fft load / store modes
 enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
-enum { ST_C64 = 0, ST_ABS2_IMG = 1 };
+enum { ST_C64 = 0, ST_ABS2_IMG = 1, ST_ABS_IMG = 2 };
 // contig_fft load / store modes
 enum { CL_C64 = 0, CL_REAL = 1 };
 enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2, CS_ABS2_MAX = 3 };
@@ -25,8 +25,8 @@ struct StridedArgs {
   long long out_plane, out_line;
   int ncols, n_in, n_out;
   float tscale;        // LD_TAU_SCALED: the sample in column t is scaled by t * tscale
-  float oscale;        // ST_ABS2_IMG: output = |v|^2 * oscale
-  float* img;          // ST_ABS2_IMG: img[plane * img_plane + n] = max over columns (may be null)
+  float oscale;        // ST_ABS2_IMG: output = |v|^2 * oscale; ST_ABS_IMG: |v| * oscale
+  float* img;          // ST_ABS*_IMG: img[plane * img_plane + n] = max over columns (may be null)
   long long img_plane;
 };
 
@@ -40,10 +40,8 @@ struct ContigArgs {
   float* img;          // CS_ABS_IMG: img[(ln % img_lines) * out_line + n] = max over lines;
                        // CS_ABS2_MAX: img[ln] = max over the line
   long long img_lines;
-  const int* bins;     // CS_BINS: out[f * out_fstride + y * row_out + x] = X[bins[f]],
-  int nbins;           //          line ln = y * row_in + x
-  long long out_fstride;
-  long long row_in, row_out;
+  const int* bins;     // CS_BINS: out[ln * nbins + f] = X[bins[f]]
+  int nbins;
 };
 
 // f-k pass 1: tau[ny][nx][nt] (float) -> half spectrum out[ny][Mx/2 + 1][nt] with
@@ -67,16 +65,19 @@ struct FkPairArgs {
   float norm;          // 1 / (Mx My Mt)
 };
 
+// Radial propagation over chunks of pixels that share the lower radial bin.
 struct RsdPropArgs {
-  const float2* Ph;    // [Nf][npix] spectra of the padded phasor planes
-  const void* Kr;      // [Nrho][Nf][Nd] radial kernel, float2 or __half2
-  const float* rho;    // [npix] pixel-to-radius map in bin units
-  const float2* w;     // [Nf] complex frequency weights
-  float2* C;           // [Nd][npix] propagated spectra
-  long long npix;
+  const float2* Ph;        // [npix][Nf] spectra of the padded phasor planes
+  const void* Kr;          // [Nrho][Nf][Nd] radial kernel, float2 or __half2
+  const float2* w;         // [Nf] complex frequency weights
+  float2* C;               // [npix][Nd] propagated spectra
+  const int* chunk_i0;     // [nchunks] lower radial bin (-1: all-zero chunk)
+  const int* chunk_pix;    // [nchunks][8] pixel index or -1
+  const float* chunk_wa;   // [nchunks][8] a (1 - alpha)
+  const float* chunk_wb;   // [nchunks][8] a alpha
+  long long nchunks;
   int Nf, Nd;
-  float rho_cut_bin;
-  int cut_idx, last_base;
+  int cut_idx;
   int kernel_fp16;
 };
 

@@ -142,7 +142,7 @@ void rsd_radial_kernel(const RsdInputs& in, const RsdGeometry& g, std::vector<do
   });
 }
 
-void rsd_radius_map(const RsdInputs& in, const RsdGeometry& g, std::vector<float>& rho) {
+void rsd_radius_map(const RsdInputs& in, const RsdGeometry& g, std::vector<double>& rho) {
   const int Mx = in.pad * in.nx, My = in.pad * in.ny;
   rho.resize((size_t)My * Mx);
   for (int u = 0; u < My; ++u) {
@@ -151,8 +151,76 @@ void rsd_radius_map(const RsdInputs& in, const RsdGeometry& g, std::vector<float
     for (int v = 0; v < Mx; ++v) {
       const int vs = v < Mx / 2 ? v : v - Mx;
       const double fv = vs / (Mx * in.dx);
-      rho[(size_t)u * Mx + v] = (float)(std::sqrt(fu * fu + fv * fv) * (g.n_rho - 1) / g.rho_max);
+      rho[(size_t)u * Mx + v] = std::sqrt(fu * fu + fv * fv) * (g.n_rho - 1) / g.rho_max;
     }
+  }
+}
+
+void rsd_build_chunks(const RsdInputs& in, const RsdGeometry& g, RsdChunks& out) {
+  std::vector<double> rho;
+  rsd_radius_map(in, g, rho);
+  const int npix = (int)rho.size();
+  struct Tap {
+    int i0, pix;
+    float wa, wb;
+  };
+  std::vector<Tap> active;
+  std::vector<int> inactive;
+  active.reserve(npix);
+  const double rc = g.rho_cut_bin;
+  for (int p = 0; p < npix; ++p) {
+    const double rt = rho[p];
+    double a;  // smoothstep taper over the last 8 bins below the cutoff
+    if (rt <= rc - 8.0) {
+      a = 1.0;
+    } else if (rt < rc) {
+      const double t = (rc - rt) / 8.0;
+      a = t * t * (3.0 - 2.0 * t);
+    } else {
+      a = 0.0;
+    }
+    if (!(a > 0.0)) {
+      inactive.push_back(p);
+      continue;
+    }
+    int i0 = (int)std::floor(rt);
+    i0 = std::max(0, std::min(i0, g.last_base));
+    const double al = rt - i0;
+    active.push_back({i0, p, (float)(a * (1.0 - al)), (float)(a * al)});
+  }
+  std::stable_sort(active.begin(), active.end(), [](const Tap& x, const Tap& y) { return x.i0 < y.i0; });
+  out.i0.clear();
+  out.pix.clear();
+  out.wa.clear();
+  out.wb.clear();
+  auto open_chunk = [&](int i0) {
+    out.i0.push_back(i0);
+    for (int j = 0; j < kChunk; ++j) {
+      out.pix.push_back(-1);
+      out.wa.push_back(0.f);
+      out.wb.push_back(0.f);
+    }
+  };
+  int fill = kChunk;
+  for (const Tap& t : active) {
+    if (fill == kChunk || out.i0.back() != t.i0) {
+      open_chunk(t.i0);
+      fill = 0;
+    }
+    const size_t s = (out.i0.size() - 1) * kChunk + fill;
+    out.pix[s] = t.pix;
+    out.wa[s] = t.wa;
+    out.wb[s] = t.wb;
+    ++fill;
+  }
+  fill = kChunk;
+  for (int p : inactive) {
+    if (fill == kChunk) {
+      open_chunk(-1);
+      fill = 0;
+    }
+    out.pix[(out.i0.size() - 1) * kChunk + fill] = p;
+    ++fill;
   }
 }
 

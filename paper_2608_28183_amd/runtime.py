@@ -78,8 +78,10 @@ class RsdPlan:
         return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
 
     def __call__(self, tau: torch.Tensor, vol=None, img=None, ws=None):
+        """vol: float32 [ny, nx, n_depth] (depth contiguous); img: float32 [ny, nx]."""
         ny, nx, nt = self.shape
         assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
+        assert vol is None or vol.shape == (ny, nx, self.n_depth)
         nlos.nlos_rsd(self.ctx.handle, self.handle, tau, vol, img, ws)
         return vol, img
 

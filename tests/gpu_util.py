@@ -43,8 +43,10 @@ def rsd_plan_for(ctx, cfg, pad=2, n_depth=None, kernel_prec="fp32", params=None)
 def run_rsd(ctx, cfg, tau, pad=2, n_depth=None, kernel_prec="fp32", params=None):
     plan, p = rsd_plan_for(ctx, cfg, pad, n_depth, kernel_prec, params)
     t = to_dev(tau.astype(np.float32))
-    vol = torch.full((p.n_depth, cfg.ny, cfg.nx), -1.0, device="cuda")
+    vol = torch.full((cfg.ny, cfg.nx, p.n_depth), -1.0, device="cuda")
     img = torch.full((cfg.ny, cfg.nx), -1.0, device="cuda")
     plan(t, vol, img, plan.workspace())
     torch.cuda.synchronize()
-    return vol.cpu().numpy().astype(np.float64), img.cpu().numpy().astype(np.float64), p
+    # the library writes vol[y][x][d]; the oracle's layout is [d][y][x]
+    v = np.moveaxis(vol.cpu().numpy().astype(np.float64), 2, 0)
+    return v, img.cpu().numpy().astype(np.float64), p

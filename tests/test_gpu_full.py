@@ -71,12 +71,12 @@ def test_rsd_full_size_c3(ctx):
     g = load_golden("rsd_c3", tau)
     say("rsd c3 full size")
     plan, p = rsd_plan_for(ctx, cfg)
-    vol = torch.empty((p.n_depth, cfg.ny, cfg.nx), device="cuda")
+    vol = torch.empty((cfg.ny, cfg.nx, p.n_depth), device="cuda")
     img = torch.empty((cfg.ny, cfg.nx), device="cuda")
     plan(to_dev(tau), vol, img, plan.workspace())
     torch.cuda.synchronize()
-    check_against_golden(g, vol.cpu().numpy(), img.cpu().numpy())
-    assert torch.equal(vol.amax(dim=0), img)
+    check_against_golden(g, np.moveaxis(vol.cpu().numpy(), 2, 0), img.cpu().numpy())
+    assert torch.equal(vol.amax(dim=2), img)
 
 
 def test_c2_raw_photons_bin_fk_rsd(ctx):
@@ -106,12 +106,12 @@ def test_c2_raw_photons_bin_fk_rsd(ctx):
     assert e < TOL and rel_l2(img.cpu().numpy(), ri) < TOL
 
     rplan, p = rsd_plan_for(ctx, cfg)
-    rvol = torch.empty((p.n_depth, cfg.ny, cfg.nx), device="cuda")
+    rvol = torch.empty((cfg.ny, cfg.nx, p.n_depth), device="cuda")
     rimg = torch.empty((cfg.ny, cfg.nx), device="cuda")
     rplan(tau_d, rvol, rimg, rplan.workspace())
     depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
     ov, oi = orsd.rsd(tau, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins, p.weights, depths)
     torch.cuda.synchronize()
-    e2 = rel_l2(rvol.cpu().numpy(), ov)
+    e2 = rel_l2(np.moveaxis(rvol.cpu().numpy(), 2, 0), ov)
     say(f"  rsd rel_l2 {e2:.2e}")
     assert e2 < TOL and rel_l2(rimg.cpu().numpy(), oi) < TOL
