@@ -102,6 +102,50 @@ def cpu_baseline_fk(cfg, fraction=8):
     return t_total * fraction, t_total
 
 
+def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=5005):
+    """Poisson stream of mixed reconstructions through the continuous-batching loop:
+    shapes uniform over {64x64x512, 128x128x1024, 256x256x512}, f-k / RSD 50/50; one run
+    all FP32, one with RSD requests split 50/50 between FP32 and FP16 kernel storage,
+    and a saturation run (all requests at 2000/s) under a 16 GiB budget."""
+    import torch
+
+    import scenes
+    from paper_2608_28183_amd.serve import GpuExecutor, Request, Server, run_stream
+
+    ex = GpuExecutor(n_slots=n_slots, geometry=scenes.serve_geometry)
+    inputs = {}
+    for s in scenes.SERVE_SHAPES:
+        for k in range(2):
+            inputs[(s, k)] = torch.from_numpy(scenes.serve_input(s, 200 + k)).cuda()
+    for s in scenes.SERVE_SHAPES:
+        ex.plan("fk", s, "fp32")
+        ex.plan("rsd", s, "fp32")
+        ex.plan("rsd", s, "fp16")
+    torch.cuda.synchronize()
+
+    def one_run(precisions, rate, budget, n):
+        stream = scenes.request_stream(n, rate, seed=seed, precisions=precisions)
+        arr = []
+        for r in stream:
+            prec = r["precision"] if r["method"] == "rsd" else "fp32"
+            arr.append((r["arrival_s"], Request(r["method"], tuple(r["shape"]), prec,
+                                                tau=inputs[(tuple(r["shape"]), r["id"] % 2)])))
+        srv = Server(ex, n_slots=n_slots, hbm_budget=budget << 30).start()
+        run_stream(srv, arr)
+        srv.stop()
+        s = srv.stats.summary()
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+
+    one_run(("fp32",), 1000.0, budget_gib, 12)  # warm-up: allocator pools, code paths
+    return {
+        "arrival_rate_hz": rate_hz, "requests": n_requests, "slots": n_slots,
+        "mix": "shapes uniform over 64x64x512, 128x128x1024, 256x256x512; f-k/RSD 50/50",
+        "fp32": one_run(("fp32",), rate_hz, budget_gib, n_requests),
+        "fp32_fp16_rsd_kernel": one_run(("fp32", "fp16"), rate_hz, budget_gib, n_requests),
+        "saturation_2000hz_16GiB": one_run(("fp32",), 2000.0, 16, 100),
+    }
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -120,6 +164,7 @@ def main():
                     choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2"])
     ap.add_argument("--prec", default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -241,6 +286,11 @@ def main():
         except MemoryError:
             cpu = None
 
+    serving = None
+    if not args.no_serve and kind == "fk":
+        print("[bench] serving run", file=sys.stderr, flush=True)
+        serving = serve_bench()
+
     line = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
@@ -248,6 +298,7 @@ def main():
         "dtype": "f32" if args.prec == "fp32" else args.prec, "data": "synthetic",
         "config": workload, "roofline": roofline, "cpu_baseline": cpu,
         "passes_ms": {k: round(v, 4) for k, v in avg_ms.items()},
+        "serving": serving,
         "step_frac_of_hbm": round(total_alg * value / units_per_step / (HBM_PEAK_GBS * 1e9), 4),
         "step_bytes": total_alg,
     }

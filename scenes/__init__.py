@@ -462,3 +462,29 @@ def checksum(a: np.ndarray) -> str:
 def config_events(name: str = "c2", order: str = "shuffled") -> np.ndarray:
     cfg = CONFIGS[name]
     return cached(f"{name}_events_{order}_{cfg.seed}", lambda: photon_events(cfg, order=order))
+
+
+# ---------------------------------------------------------------------------
+# serving mix: geometry and inputs per request shape
+# ---------------------------------------------------------------------------
+
+SERVE_CONFIG_OF_SHAPE = {(64, 64, 512): "c2", (128, 128, 1024): "c3", (256, 256, 512): "c4"}
+
+
+def serve_config(shape) -> Config:
+    """The config whose geometry a serving request of this shape uses."""
+    return CONFIGS[SERVE_CONFIG_OF_SHAPE[tuple(shape)]]
+
+
+def serve_geometry(shape) -> dict:
+    cfg = serve_config(shape)
+    return dict(wall_w=cfg.wall_w, wall_h=cfg.wall_h, bin_ps=cfg.bin_ps, pad=cfg.pad,
+                dx=cfg.dx, dy=cfg.dy, rsd=rsd_params(cfg))
+
+
+def serve_input(shape, seed: int) -> np.ndarray:
+    """A fast seeded input of a serving shape: three point reflectors in the config's
+    depth range, Poisson counts (content does not affect the work)."""
+    base = serve_config(shape)
+    cfg = dataclasses.replace(base, scene="points3", seed=seed)
+    return transient(cfg, seed=seed)

@@ -1,0 +1,55 @@
+"""Serving loop on the GPU: concurrent mixed requests give the same results as alone."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from paper_2608_28183_amd import runtime
+from paper_2608_28183_amd.serve import GpuExecutor, Request, Server
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_results_alone_equal_results_in_the_mix(lib):
+    shapes = [(64, 64, 512), (128, 128, 1024), (256, 256, 512)]
+    combos = [("fk", s, "fp32") for s in shapes] + [("rsd", s, p) for s in shapes
+                                                    for p in ("fp32", "fp16")]
+    inputs = {(s, k): torch.from_numpy(scenes.serve_input(s, 100 + k)).cuda()
+              for s in shapes for k in range(2)}
+    torch.cuda.synchronize()
+    ex = GpuExecutor(n_slots=4, geometry=scenes.serve_geometry)
+    budget = 12 << 30
+    srv = Server(ex, n_slots=4, hbm_budget=budget)
+    reqs = []
+    for rep in range(2):
+        for (m, s, p) in combos:
+            for k in range(2):
+                reqs.append(Request(m, s, p, tau=inputs[(s, k)]))
+    # plans first (resident), then the burst
+    for r in reqs:
+        ex.plan(r.method, r.shape, r.precision)
+    srv.start()
+    futs = [srv.submit(r) for r in reqs]
+    outs = [f.result(timeout=300) for f in futs]
+    srv.stop()
+    st = srv.stats.summary()
+    say(f"serve burst: {st}")
+    assert st["completed"] == len(reqs)
+    assert srv.stats.peak_bytes <= budget
+    assert srv.stats.peak_inflight >= 2          # work from several requests overlapped
+
+    # each request alone on one stream, the same plan
+    ctx = runtime.Context(0)
+    for r, (vol, img) in zip(reqs, outs):
+        p = ex.plan(r.method, r.shape, r.precision)
+        v1 = torch.empty_like(vol)
+        i1 = torch.empty_like(img)
+        p.ctx = ctx
+        if r.method == "fk":
+            runtime.nlos.nlos_fk(ctx.handle, p.handle, r.tau, v1, i1, p.workspace())
+        else:
+            runtime.nlos.nlos_rsd(ctx.handle, p.handle, r.tau, v1, i1, p.workspace())
+        torch.cuda.synchronize()
+        assert torch.equal(v1, vol) and torch.equal(i1, img), (r.method, r.shape, r.precision)
