@@ -26,15 +26,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 F32_VALU_PEAK_TFLOPS = 157.3
 
 
-def fk_pass_bytes(ny, nx, nt, pad):
+def fk_pass_bytes(ny, nx, nt, pad, c=8):
     """Algorithmic HBM bytes of each f-k pass of the schedule: every pruned intermediate
-    written once and read once as complex64 (half spectra kx <= Mx/2 up to the column
-    pass, the z-IFFT last on the cropped ny x nx columns), tau read and vol written as
-    float32."""
+    written once and read once as c-byte complex values (8: FP32; 4: FP16 / BF16) -- half spectra
+    kx <= Mx/2 up to the column pass, the z-IFFT last on the cropped ny x nx columns --
+    tau read and vol written as float32."""
     Mx, My = pad * nx, pad * ny
     Mh = Mx // 2 + 1
     nwork = (Mx // 2 - 1) * My + 2 * (My // 2 + 1)
-    c = 8
     return {
         "fk_x": 4 * ny * nx * nt + c * ny * Mh * nt,
         "fk_y": c * ny * Mh * nt + c * My * Mh * nt,
@@ -72,7 +71,7 @@ def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
     }
 
 
-def cpu_baseline_fk(cfg, fraction=8):
+def cpu_baseline_fk(cfg, fraction=2):
     """The FP64 oracle, untuned, on a bounded sample of the f-k workload: each oracle
     step runs on 1/fraction of its independent slices of the full-size padded volume
     (random data of the same shape: the matrix-DFT cost does not depend on values),
@@ -104,9 +103,9 @@ def cpu_baseline_fk(cfg, fraction=8):
 
 def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=5005):
     """Poisson stream of mixed reconstructions through the continuous-batching loop:
-    shapes uniform over {64x64x512, 128x128x1024, 256x256x512}, f-k / RSD 50/50; one run
-    all FP32, one with RSD requests split 50/50 between FP32 and FP16 kernel storage,
-    and a saturation run (all requests at 2000/s) under a 16 GiB budget."""
+    shapes uniform over {64x64x512, 128x128x1024, 256x256x512}, f-k / RSD 50/50; runs
+    all FP32, all FP16 and 50/50 mixed, and a saturation run (all requests at 2000/s)
+    under a 16 GiB budget."""
     import torch
 
     import scenes
@@ -118,16 +117,16 @@ def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=500
         for k in range(2):
             inputs[(s, k)] = torch.from_numpy(scenes.serve_input(s, 200 + k)).cuda()
     for s in scenes.SERVE_SHAPES:
-        ex.plan("fk", s, "fp32")
-        ex.plan("rsd", s, "fp32")
-        ex.plan("rsd", s, "fp16")
+        for m in ("fk", "rsd"):
+            for p in ("fp32", "fp16"):
+                ex.plan(m, s, p)
     torch.cuda.synchronize()
 
     def one_run(precisions, rate, budget, n):
         stream = scenes.request_stream(n, rate, seed=seed, precisions=precisions)
         arr = []
         for r in stream:
-            prec = r["precision"] if r["method"] == "rsd" else "fp32"
+            prec = r["precision"]
             arr.append((r["arrival_s"], Request(r["method"], tuple(r["shape"]), prec,
                                                 tau=inputs[(tuple(r["shape"]), r["id"] % 2)])))
         srv = Server(ex, n_slots=n_slots, hbm_budget=budget << 30).start()
@@ -139,9 +138,11 @@ def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=500
     one_run(("fp32",), 1000.0, budget_gib, 12)  # warm-up: allocator pools, code paths
     return {
         "arrival_rate_hz": rate_hz, "requests": n_requests, "slots": n_slots,
-        "mix": "shapes uniform over 64x64x512, 128x128x1024, 256x256x512; f-k/RSD 50/50",
+        "mix": "shapes uniform over 64x64x512, 128x128x1024, 256x256x512; f-k/RSD 50/50; "
+               "fp16 = FP16 f-k intermediates, FP16 RSD kernel",
         "fp32": one_run(("fp32",), rate_hz, budget_gib, n_requests),
-        "fp32_fp16_rsd_kernel": one_run(("fp32", "fp16"), rate_hz, budget_gib, n_requests),
+        "fp16": one_run(("fp16",), rate_hz, budget_gib, n_requests),
+        "fp32_fp16_mixed": one_run(("fp32", "fp16"), rate_hz, budget_gib, n_requests),
         "saturation_2000hz_16GiB": one_run(("fp32",), 2000.0, 16, 100),
     }
 
@@ -162,7 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
                     choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2"])
-    ap.add_argument("--prec", default="fp32")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="f-k storage precision of the complex intermediates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
@@ -197,7 +199,9 @@ def main():
         vol = torch.empty((ny, nx, nt), device=dev)
         img = torch.empty((ny, nx), device=dev)
         step = lambda: plan(tau, vol, img, ws)  # noqa: E731
-        pass_bytes = fk_pass_bytes(ny, nx, nt, cfg.pad)
+        pass_bytes = fk_pass_bytes(ny, nx, nt, cfg.pad, 8 if args.prec == "fp32" else 4)
+        if args.prec == "fp16":
+            pass_bytes["fk_scale"] = 4 * ny * nx * nt  # the bound's read of tau
         metric, unit = "fk_volumes_per_s", "volumes/s"
         units_per_step = 1
         workload = {"workload": f"f-k migration {ny}x{nx}x{nt} padded x{cfg.pad} "
@@ -276,11 +280,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and kind == "fk":
         try:
-            est, spent = cpu_baseline_fk(cfg)
+            frac = 2
+            est, spent = cpu_baseline_fk(cfg, frac)
             cpu = {"value": round(1.0 / est, 6), "unit": unit, "cores": blas_threads() or
                    len(os.sched_getaffinity(0)), "kind": "oracle",
-                   "sample": f"every FP64 oracle step on 1/8 of its independent slices of the "
-                             f"{cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt} volume, scaled x8 "
+                   "sample": f"every FP64 oracle step on 1/{frac} of its independent slices of the "
+                             f"{cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt} volume, scaled x{frac} "
                              f"({spent:.1f} s of CPU time measured)",
                    "host_cpus": len(os.sched_getaffinity(0))}
         except MemoryError:

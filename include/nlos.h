@@ -88,7 +88,8 @@ typedef enum {
   NLOS_PASS_RSD_YI = 11,       /* RSD: y-IFFT per depth */
   NLOS_PASS_RSD_XI = 12,       /* RSD: x-IFFT, |.|, max over depth */
   NLOS_PASS_FK_ZI = 13,        /* f-k pass 6: z-IFFT, |.|^2, max over depth */
-  NLOS_PASS_COUNT = 14
+  NLOS_PASS_FK_SCALE = 14,     /* f-k FP16 storage scales from the input bound */
+  NLOS_PASS_COUNT = 15
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
@@ -144,14 +145,23 @@ typedef struct {
   double wall_h_m;         /* along y (m); dy = wall_h_m / ny */
   double bin_ps;           /* time-bin width (ps) */
   int pad;                 /* 1 (no padding) or 2 (x2 zero padding on every axis) */
-  nlos_precision prec;     /* storage of the complex intermediates */
+  nlos_precision prec;     /* storage of the complex intermediates (Section 4.2, data
+                            quantization); arithmetic is FP32 in every case.
+                            NLOS_FP32: 8-byte complex values.  NLOS_BF16: 4-byte, stored
+                            as is (FP32's exponent range).  NLOS_FP16: 4-byte, each
+                            intermediate stored times a power of two computed on the
+                            device from the bound B = sum |tau| t/(nt-1) on its
+                            magnitude (forward: B, Stolt output: B/(Mx My Mt), times M
+                            per inverse axis), so stored values stay below 2^14;
+                            requires a finite B */
 } nlos_fk_desc;
 
 /* Host-only validation: dims >= 1, nt >= 2, pad in {1, 2}, pad*nx, pad*ny and
  * pad*nt powers of two in [8, 2048] (else NLOS_ERR_UNSUPPORTED), positive
  * finite geometry. */
 nlos_status nlos_fk_check(const nlos_fk_desc *desc);
-/* Exact device workspace one nlos_fk call needs (host only). */
+/* Exact device workspace one nlos_fk call needs (host only): about half the FP32
+ * figure for NLOS_FP16 / NLOS_BF16 (FP16 adds 4.3 KB of scale scratch). */
 nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc *desc, size_t *bytes);
 nlos_status nlos_fk_plan_create(nlos_ctx *ctx, const nlos_fk_desc *desc, nlos_fk_plan **out);
 nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
@@ -164,8 +174,10 @@ nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
  *   frequency sample; inverse 3D DFT normalised by 1/(Mx My Mt).
  * Writes d_vol[ny][nx][nt] = |Psi|^2 on the unpadded grid and d_img[ny][nx] =
  * max over depth of d_vol; either output may be NULL (not both).  d_ws is
- * device workspace of ws_bytes >= nlos_fk_workspace_bytes (NULL: the context
- * pool is used and grown as needed).  Inputs are not modified. */
+ * 256-byte aligned device workspace of ws_bytes >= nlos_fk_workspace_bytes
+ * (NULL: the context pool is used and grown as needed; misaligned:
+ * NLOS_ERR_INVALID_ARG; too small: NLOS_ERR_OUT_OF_MEMORY).  d_tau must be 8-byte
+ * aligned.  Inputs are not modified. */
 nlos_status nlos_fk(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_vol,
                     float *d_img, void *d_ws, size_t ws_bytes);
 

@@ -62,11 +62,6 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-if __name__ == "__main__":
-    build(verbose=True)
-    sys.exit(0)
-
-
 def source_sha() -> str:
     """sha256 over the kernel and host sources (identifies the built code)."""
     import hashlib
@@ -76,3 +71,8 @@ def source_sha() -> str:
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -54,25 +54,18 @@ __device__ __forceinline__ void apply_stage(float2* v, int, const TwRegs<S>& tw)
 }
 
 // v holds the stage-0 inputs (element stage_in_index<N, R0, E>(p, b, r) at v[b*R0 + r]).
-// Runs every stage; outputs go through store(n, value).  When SYNC_BEFORE_STORE is
-// set a barrier separates the last LDS read from the stores (for stores into LDS).
-template <class S, bool INV, bool SYNC_BEFORE_STORE, class Idx, class TW, class Store>
-__device__ __forceinline__ void fft_run(float2* v, int p, float2* lds, Idx idx, const TW& tw,
-                                        Store store) {
+// Runs every stage; the last stage's outputs stay in v in the order emit_last visits.
+template <class S, bool INV, class Idx, class TW>
+__device__ __forceinline__ void fft_stages(float2* v, int p, float2* lds, Idx idx, const TW& tw) {
   constexpr int N = S::R0 * S::R1 * S::R2;
   constexpr int E = S::E;
   stage_compute<N, S::R0, 1, E, INV>(v, p, nullptr);
-  if constexpr (S::NSTAGE == 1) {
-    if constexpr (SYNC_BEFORE_STORE) __syncthreads();
-    emit<N, S::R0, 1, E>(v, p, store);
-  } else {
+  if constexpr (S::NSTAGE >= 2) {
     write_lds<N, S::R0, 1, E>(v, p, lds, idx);
     __syncthreads();
     read_lds<N, S::R1, E>(v, p, lds, idx);
     if constexpr (S::NSTAGE == 2) {
       apply_stage<S, 1, INV>(v, p, tw);
-      if constexpr (SYNC_BEFORE_STORE) __syncthreads();
-      emit<N, S::R1, S::R0, E>(v, p, store);
     } else {
       __syncthreads();
       apply_stage<S, 1, INV>(v, p, tw);
@@ -80,10 +73,53 @@ __device__ __forceinline__ void fft_run(float2* v, int p, float2* lds, Idx idx, 
       __syncthreads();
       read_lds<N, S::R2, E>(v, p, lds, idx);
       apply_stage<S, 2, INV>(v, p, tw);
-      if constexpr (SYNC_BEFORE_STORE) __syncthreads();
-      emit<N, S::R2, S::R0 * S::R1, E>(v, p, store);
     }
   }
+}
+
+// Calls store(n, value) for every output element held by thread p after fft_stages.
+template <class S, class Store>
+__device__ __forceinline__ void emit_last(const float2* v, int p, Store store) {
+  constexpr int N = S::R0 * S::R1 * S::R2;
+  constexpr int E = S::E;
+  if constexpr (S::NSTAGE == 1) emit<N, S::R0, 1, E>(v, p, store);
+  else if constexpr (S::NSTAGE == 2) emit<N, S::R1, S::R0, E>(v, p, store);
+  else emit<N, S::R2, S::R0 * S::R1, E>(v, p, store);
+}
+
+// All stages, then store(n, value) for every output.  SYNC_BEFORE_STORE puts a
+// barrier between the last LDS read and the stores (for stores into LDS).
+template <class S, bool INV, bool SYNC_BEFORE_STORE, class Idx, class TW, class Store>
+__device__ __forceinline__ void fft_run(float2* v, int p, float2* lds, Idx idx, const TW& tw,
+                                        Store store) {
+  fft_stages<S, INV>(v, p, lds, idx, tw);
+  if constexpr (SYNC_BEFORE_STORE) __syncthreads();
+  emit_last<S>(v, p, store);
+}
+
+// First-stage inputs of thread p without per-element branches: raw[r] = ld(n) for
+// element n = p + r P of the line when n < n_in and ok, zero otherwise, so that all of
+// the thread's loads are issued back to back.  The zero padding of a line is either
+// absent (n_in >= N) or its upper half (n_in = N/2: exactly r >= E/2); other lengths
+// load a clamped in-bounds element and select.  ld must accept any n in [0, n_in).
+template <class S, class R, class Ld>
+__device__ __forceinline__ void load_first_stage(R* raw, int p, int n_in, bool ok, R zero, Ld ld) {
+  constexpr int N = S::R0 * S::R1 * S::R2, E = S::E, P = S::P;
+  static_assert(S::R0 == E, "first-stage radix equals the samples per thread");
+  if (n_in >= N) {
+    static_for<E>([&](auto r_) { raw[decltype(r_)::value] = ld(p + decltype(r_)::value * P); });
+  } else if (2 * n_in == N) {
+    static_for<E / 2>([&](auto r_) { raw[decltype(r_)::value] = ld(p + decltype(r_)::value * P); });
+    static_for<E / 2>([&](auto r_) { raw[E / 2 + decltype(r_)::value] = zero; });
+  } else {
+    static_for<E>([&](auto r_) {
+      constexpr int r = decltype(r_)::value;
+      const int n = p + r * P;
+      const R x = ld(n < n_in ? n : 0);
+      raw[r] = n < n_in ? x : zero;
+    });
+  }
+  if (!ok) static_for<E>([&](auto r_) { raw[decltype(r_)::value] = zero; });
 }
 
 // ---------------------------------------------------------------------------

@@ -62,7 +62,7 @@ constexpr double cx_cospi2(long k, long n, bool want_sin) {
   if (k < 0) k += n;
   long q = (4 * k) / n;             // quadrant
   long rem = 4 * k - q * n;         // angle within quadrant = (pi/2) rem / n
-  double c, s;
+  double c = 0.0, s = 0.0;
   if (2 * rem <= n) {
     double a = 0.5 * cx_pi * double(rem) / double(n);
     c = cx_cos_small(a);

@@ -8,14 +8,16 @@
 // The f-k specific passes (real-input x pass, paired column pass) are in k_fk.hip.
 #include "fft_block.hpp"
 #include "nlos_internal.hpp"
+#include "prec.hpp"
 
 namespace nlos {
 
-template <int N, int E, int T_, bool INV, int LD, int ST>
+template <int N, int E, int T_, bool INV, int LD, int ST, int SP = SP_F32>
 __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(StridedArgs a,
                                                                               const float2* __restrict__ tw) {
   using C = StridedCfg<N, E, T_>;
   using S = typename C::S;
+  using ST_ = Stor<SP>;
   constexpr int T = C::T;
   constexpr int E_ = S::E;
   __shared__ float2 lds[C::LDS_ELEMS];
@@ -27,24 +29,50 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
   const bool colok = col < a.ncols;
 
   float2 v[E_];
-  static_for<E / S::R0>([&](auto b_) {
-    static_for<S::R0>([&](auto r_) {
-      constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-      const int n = stage_in_index<N, S::R0, E_>(p, b, r);
-      float2 x = make_float2(0.f, 0.f);
-      if (colok && n < a.n_in) {
-        const long long i = plane * a.in_plane + (long long)n * a.in_line + col;
-        if constexpr (LD == LD_TAU_SCALED) {
-          x.x = static_cast<const float*>(a.in)[i] * (float(col) * a.tscale);
-        } else {
-          x = static_cast<const float2*>(a.in)[i];
+  if constexpr (SP == SP_F32 || LD == LD_TAU_SCALED) {
+    static_for<E / S::R0>([&](auto b_) {
+      static_for<S::R0>([&](auto r_) {
+        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+        const int n = stage_in_index<N, S::R0, E_>(p, b, r);
+        float2 x = make_float2(0.f, 0.f);
+        if (colok && n < a.n_in) {
+          const long long i = plane * a.in_plane + (long long)n * a.in_line + col;
+          if constexpr (LD == LD_TAU_SCALED) {
+            x.x = static_cast<const float*>(a.in)[i] * (float(col) * a.tscale);
+          } else {
+            x = static_cast<const float2*>(a.in)[i];
+          }
         }
-      }
-      v[b * S::R0 + r] = x;
+        v[b * S::R0 + r] = x;
+      });
     });
-  });
+  } else {
+    // four-byte storage: raw loads first, conversion after, so that all loads of the
+    // thread are in flight together
+    typename ST_::R raw[E_];
+    // addresses relative to row p, so that row r P + p is a scalar multiple of in_line away
+    const typename ST_::T* in = static_cast<const typename ST_::T*>(a.in) + plane * a.in_plane +
+                                (colok ? col : 0) + (long long)p * a.in_line;
+    load_first_stage<S>(raw, p, a.n_in, colok, ST_::zero(),
+                        [&](int n) { return ST_::raw(in, (long long)(n - p) * a.in_line); });
+    const int e = SP == SP_F16 ? -*a.e_in : 0;
+#pragma unroll
+    for (int j = 0; j < E_; ++j) {
+      v[j] = ST_::cvt(raw[j]);
+      if constexpr (SP == SP_F16) v[j] = ldexp2(v[j], e);
+    }
+  }
 
   auto idx = [&](int n) { return n * C::LDS_W + c; };
+  if constexpr (ST == ST_C64 && SP != SP_F32) {
+    const int e = SP == SP_F16 ? *a.e_out : 0;
+    fft_run<S, INV, false>(v, p, lds, idx, tw, [&](int n, float2 val) {
+      if (colok && n < a.n_out)
+        ST_::st(static_cast<typename ST_::T*>(a.out), plane * a.out_plane + (long long)n * a.out_line + col,
+                SP == SP_F16 ? ldexp2(val, e) : val);
+    });
+    return;
+  }
   auto store = [&](int n, float2 val) {
     if constexpr (ST == ST_C64) {
       if (colok && n < a.n_out)
@@ -78,7 +106,7 @@ struct ContigTune {
   static constexpr int E = default_e(N);
 };
 
-template <int N, bool INV, int LD, int ST>
+template <int N, bool INV, int LD, int ST, int SP = SP_F32>
 __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void contig_fft(
     ContigArgs a, const float2* __restrict__ tw) {
   using C = ContigCfg<N, ContigTune<N>::E>;
@@ -91,24 +119,37 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   const int p = tid % P;
   const long long line = (long long)blockIdx.x * C::L + l;
   const bool lineok = line < a.nlines;
-
   float2 v[E];
-  static_for<E / S::R0>([&](auto b_) {
-    static_for<S::R0>([&](auto r_) {
-      constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-      const int n = stage_in_index<N, S::R0, E>(p, b, r);
-      float2 x = make_float2(0.f, 0.f);
-      if (lineok && n < a.n_in) {
-        const long long i = line * a.in_line + n;
-        if constexpr (LD == CL_REAL) {
-          x.x = static_cast<const float*>(a.in)[i];
-        } else {
-          x = static_cast<const float2*>(a.in)[i];
+  if constexpr (SP == SP_F32 || LD == CL_REAL) {
+    static_for<E / S::R0>([&](auto b_) {
+      static_for<S::R0>([&](auto r_) {
+        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+        const int n = stage_in_index<N, S::R0, E>(p, b, r);
+        float2 x = make_float2(0.f, 0.f);
+        if (lineok && n < a.n_in) {
+          const long long i = line * a.in_line + n;
+          if constexpr (LD == CL_REAL) {
+            x.x = static_cast<const float*>(a.in)[i];
+          } else {
+            x = static_cast<const float2*>(a.in)[i];
+          }
         }
-      }
-      v[b * S::R0 + r] = x;
+        v[b * S::R0 + r] = x;
+      });
     });
-  });
+  } else {
+    // four-byte storage: raw loads first, conversion after
+    using ST_ = Stor<SP>;
+    typename ST_::R raw[E];
+    const typename ST_::T* in = static_cast<const typename ST_::T*>(a.in) + (lineok ? line : 0) * a.in_line;
+    load_first_stage<S>(raw, p, a.n_in, lineok, ST_::zero(), [&](int n) { return ST_::raw(in, n); });
+    const int e = SP == SP_F16 ? -*a.e_in : 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      v[j] = ST_::cvt(raw[j]);
+      if constexpr (SP == SP_F16) v[j] = ldexp2(v[j], e);
+    }
+  }
 
   float2* my = lds + (NEED_LDS ? l * C::LSTRIDE : 0);
   auto idx = [&](int n) { return swz(n); };
@@ -165,42 +206,52 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
 
 // (samples per thread, columns per block) of the strided passes, from timing sweeps at
 // 512-point lines (256x256x512 f-k): forward y pass E=16 T=16, inverse passes E=8 T=16;
-// 256-point lines use 32 columns (256-byte rows)
-template <int N, bool INV, int LD, int ST>
+// 256-point lines use 32 columns (256-byte rows).  With four-byte storage the forward
+// pass doubles its columns (128-byte row segments); the inverse passes keep theirs,
+// whose higher occupancy measured faster.
+template <int N, bool INV, int LD, int ST, int SP = SP_F32>
 struct StridedTune {
+  static constexpr bool WIDE = SP != SP_F32 && !INV;
   static constexpr int E = (N == 512) ? (INV ? 8 : 16) : default_e(N);
-  static constexpr int T = (N == 512) ? 16 : (N == 256 ? 32 : default_t(N));
+  static constexpr int T = (N == 512) ? (WIDE ? 32 : 16) : (N == 256 ? (WIDE ? 64 : 32) : default_t(N));
 };
 
-template <int N, bool INV, int LD, int ST, int E = StridedTune<N, INV, LD, ST>::E,
-          int T = StridedTune<N, INV, LD, ST>::T>
+template <int N, bool INV, int LD, int ST, int SP = SP_F32, int E = StridedTune<N, INV, LD, ST, SP>::E,
+          int T = StridedTune<N, INV, LD, ST, SP>::T>
 static hipError_t launch_strided_n(const StridedArgs& a, int nplanes, const float2* tw,
                                    hipStream_t s) {
   using C = StridedCfg<N, E, T>;
   dim3 grid((a.ncols + C::T - 1) / C::T, nplanes);
-  hipLaunchKernelGGL((strided_fft<N, E, T, INV, LD, ST>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((strided_fft<N, E, T, INV, LD, ST, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-template <bool INV, int LD, int ST>
+template <bool INV, int LD, int ST, int SP = SP_F32>
 static hipError_t launch_strided_inv(int n, const StridedArgs& a, int nplanes, const float2* tw,
                                      hipStream_t s) {
   switch (n) {
-    case 8: return launch_strided_n<8, INV, LD, ST>(a, nplanes, tw, s);
-    case 16: return launch_strided_n<16, INV, LD, ST>(a, nplanes, tw, s);
-    case 32: return launch_strided_n<32, INV, LD, ST>(a, nplanes, tw, s);
-    case 64: return launch_strided_n<64, INV, LD, ST>(a, nplanes, tw, s);
-    case 128: return launch_strided_n<128, INV, LD, ST>(a, nplanes, tw, s);
-    case 256: return launch_strided_n<256, INV, LD, ST>(a, nplanes, tw, s);
-    case 512: return launch_strided_n<512, INV, LD, ST>(a, nplanes, tw, s);
-    case 1024: return launch_strided_n<1024, INV, LD, ST>(a, nplanes, tw, s);
-    case 2048: return launch_strided_n<2048, INV, LD, ST>(a, nplanes, tw, s);
+    case 8: return launch_strided_n<8, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 16: return launch_strided_n<16, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 32: return launch_strided_n<32, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 64: return launch_strided_n<64, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 128: return launch_strided_n<128, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 256: return launch_strided_n<256, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 512: return launch_strided_n<512, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 1024: return launch_strided_n<1024, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 2048: return launch_strided_n<2048, INV, LD, ST, SP>(a, nplanes, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
-                          const float2* tw, hipStream_t s) {
+                          const float2* tw, hipStream_t s, int sp) {
+  if (sp == SP_F16 && ld == LD_C64 && st == ST_C64)
+    return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_F16>(n, a, nplanes, tw, s)
+                   : launch_strided_inv<false, LD_C64, ST_C64, SP_F16>(n, a, nplanes, tw, s);
+  if (sp == SP_BF16 && ld == LD_C64 && st == ST_C64)
+    return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_BF16>(n, a, nplanes, tw, s)
+                   : launch_strided_inv<false, LD_C64, ST_C64, SP_BF16>(n, a, nplanes, tw, s);
+  if (sp != SP_F32) return hipErrorInvalidValue;
   if (!inverse && ld == LD_TAU_SCALED && st == ST_C64)
     return launch_strided_inv<false, LD_TAU_SCALED, ST_C64>(n, a, nplanes, tw, s);
   if (!inverse && ld == LD_C64 && st == ST_C64)
@@ -214,32 +265,37 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
   return hipErrorInvalidValue;
 }
 
-template <int N, bool INV, int LD, int ST>
+template <int N, bool INV, int LD, int ST, int SP = SP_F32>
 static hipError_t launch_contig_n(const ContigArgs& a, const float2* tw, hipStream_t s) {
   using C = ContigCfg<N, ContigTune<N>::E>;
   dim3 grid((unsigned)((a.nlines + C::L - 1) / C::L));
-  hipLaunchKernelGGL((contig_fft<N, INV, LD, ST>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((contig_fft<N, INV, LD, ST, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-template <bool INV, int LD, int ST>
+template <bool INV, int LD, int ST, int SP = SP_F32>
 static hipError_t launch_contig_inv(int n, const ContigArgs& a, const float2* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_contig_n<8, INV, LD, ST>(a, tw, s);
-    case 16: return launch_contig_n<16, INV, LD, ST>(a, tw, s);
-    case 32: return launch_contig_n<32, INV, LD, ST>(a, tw, s);
-    case 64: return launch_contig_n<64, INV, LD, ST>(a, tw, s);
-    case 128: return launch_contig_n<128, INV, LD, ST>(a, tw, s);
-    case 256: return launch_contig_n<256, INV, LD, ST>(a, tw, s);
-    case 512: return launch_contig_n<512, INV, LD, ST>(a, tw, s);
-    case 1024: return launch_contig_n<1024, INV, LD, ST>(a, tw, s);
-    case 2048: return launch_contig_n<2048, INV, LD, ST>(a, tw, s);
+    case 8: return launch_contig_n<8, INV, LD, ST, SP>(a, tw, s);
+    case 16: return launch_contig_n<16, INV, LD, ST, SP>(a, tw, s);
+    case 32: return launch_contig_n<32, INV, LD, ST, SP>(a, tw, s);
+    case 64: return launch_contig_n<64, INV, LD, ST, SP>(a, tw, s);
+    case 128: return launch_contig_n<128, INV, LD, ST, SP>(a, tw, s);
+    case 256: return launch_contig_n<256, INV, LD, ST, SP>(a, tw, s);
+    case 512: return launch_contig_n<512, INV, LD, ST, SP>(a, tw, s);
+    case 1024: return launch_contig_n<1024, INV, LD, ST, SP>(a, tw, s);
+    case 2048: return launch_contig_n<2048, INV, LD, ST, SP>(a, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a, const float2* tw,
-                         hipStream_t s) {
+                         hipStream_t s, int sp) {
+  if (sp == SP_F16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
+    return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16>(n, a, tw, s);
+  if (sp == SP_BF16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
+    return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16>(n, a, tw, s);
+  if (sp != SP_F32) return hipErrorInvalidValue;
   if (!inverse && ld == CL_REAL && st == CS_BINS)
     return launch_contig_inv<false, CL_REAL, CS_BINS>(n, a, tw, s);
   if (!inverse && ld == CL_C64 && st == CS_C64)

@@ -16,6 +16,7 @@
 //                  free), which needs a quarter of the z transforms.
 #include "fft_block.hpp"
 #include "nlos_internal.hpp"
+#include "prec.hpp"
 
 namespace nlos {
 
@@ -23,7 +24,7 @@ namespace nlos {
 // pass 1: real x-FFT with time scaling and zero padding
 // ---------------------------------------------------------------------------
 
-template <int N, int E, int T>
+template <int N, int E, int T, int SP = SP_F32>
 __global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c(FkXArgs a,
                                                                           const float2* __restrict__ tw) {
   using C = StridedCfg<N, E, T>;
@@ -54,8 +55,21 @@ __global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c(FkXArg
   auto idx = [&](int n) { return n * C::LDS_W + c; };
   fft_run<S, false, true>(v, p, lds, idx, tw, [&](int n, float2 val) { lds[idx(n)] = val; });
   __syncthreads();
+  if constexpr (SP != SP_F32) {
+    if (!colok) return;
+    using ST_ = Stor<SP>;
+    typename ST_::T* out = static_cast<typename ST_::T*>(a.out) + y * a.out_plane + 2 * cc;
+    const float h = SP == SP_F16 ? ldexpf(0.5f, *a.e_out) : 0.5f;
+    for (int k = p; k <= N / 2; k += P) {
+      const float2 zk = lds[idx(k)];
+      const float2 zm = lds[idx((N - k) & (N - 1))];
+      ST_::st2(out, (long long)k * a.nt, make_float2(h * (zk.x + zm.x), h * (zk.y - zm.y)),
+               make_float2(h * (zk.y + zm.y), h * (zm.x - zk.x)));
+    }
+    return;
+  }
   if (!colok) return;
-  float4* out = reinterpret_cast<float4*>(a.out + y * a.out_plane + 2 * cc);
+  float4* out = reinterpret_cast<float4*>(static_cast<float2*>(a.out) + y * a.out_plane + 2 * cc);
   for (int k = p; k <= N / 2; k += P) {
     const float2 zk = lds[idx(k)];
     const float2 zm = lds[idx((N - k) & (N - 1))];
@@ -100,11 +114,12 @@ __device__ __forceinline__ PairItem pair_item(long long w, int Mx, int My) {
   return it;
 }
 
-template <int N, int E_ = default_e(N)>
+template <int N, int E_ = default_e(N), int SP = SP_F32>
 __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(FkPairArgs a,
                                                                              const float2* __restrict__ tw) {
   using C = ContigCfg<N, E_>;
   using S = typename C::S;
+  using ST_ = Stor<SP>;
   constexpr int E = S::E, P = C::P, HALF = N / 2;
   __shared__ float2 lds[C::LDS_ELEMS];
   const int tid = threadIdx.x;
@@ -118,18 +133,30 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
     const long long w = g * C::L + l;
     const bool ok = w < a.nwork;
     const PairItem it = pair_item(ok ? w : 0, a.Mx, a.My);
-    const float2* src = a.in + (long long)it.ky * a.in_row + (long long)it.kx * a.nt;
-
+    const long long src = (long long)it.ky * a.in_row + (long long)it.kx * a.nt;
     float2 v[E];
-    static_for<E / S::R0>([&](auto b_) {
-      static_for<S::R0>([&](auto r_) {
-        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-        const int n = stage_in_index<N, S::R0, E>(p, b, r);
-        float2 x = make_float2(0.f, 0.f);
-        if (ok && n < a.nt) x = src[n];
-        v[b * S::R0 + r] = x;
-      });
-    });
+    {
+      // raw loads first, conversion after, so that all loads of the column are in
+      // flight together
+      typename ST_::R raw[E];
+      const typename ST_::T* in = static_cast<const typename ST_::T*>(a.in) + src;
+      if constexpr (SP == SP_F32) {
+        // per-element guards measured faster than the branch-free form for 8-byte loads
+        static_for<E>([&](auto r_) {
+          constexpr int r = decltype(r_)::value;
+          const int n = p + r * P;
+          raw[r] = (ok && n < a.nt) ? in[n] : ST_::zero();
+        });
+      } else {
+        load_first_stage<S>(raw, p, a.nt, ok, ST_::zero(), [&](int n) { return ST_::raw(in, n); });
+      }
+      const int e = SP == SP_F16 ? -*a.e_in : 0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        v[j] = ST_::cvt(raw[j]);
+        if constexpr (SP == SP_F16) v[j] = ldexp2(v[j], e);
+      }
+    }
     __syncthreads();  // the previous item's last LDS reads are done
     fft_run<S, false, true>(v, p, my, idx, tw, [&](int n, float2 val) { my[swz(n)] = val; });
     __syncthreads();
@@ -142,43 +169,117 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
     const double A = ax * ax + ay * ay;
     // the remapped column and its mirror go straight to W3 (kz < nt; kz >= Mt/2 and
     // kz = 0 are zero)
-    float2* dst = a.out + (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
-    float2* dst2 = a.out + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt;
+    const long long dst = (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
+    const long long dst2 = (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt;
     const bool ok2 = ok && it.has_mirror;
-    static_for<E / S::R0>([&](auto b_) {
-      static_for<S::R0>([&](auto r_) {
-        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-        const int kz = stage_in_index<N, S::R0, E>(p, b, r);
-        if (kz < a.nt) {
-          float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
-          if (kz > 0 && kz < HALF) {
-            const double q2 = A + double(kz * kz);
-            const float qf = __builtin_amdgcn_sqrtf((float)q2);
-            const float rq = __builtin_amdgcn_rcpf(qf);
-            const double q0 = (double)qf;
-            const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
-            if (q <= double(HALF - 1)) {
-              const double fl = floor(q);
-              const int i0 = int(fl);
-              const int i1 = i0 + 1 < HALF ? i0 + 1 : HALF - 1;
-              const float fr = float(q - fl);
-              const float jac = float(kz) * rq * a.norm;
-              // column (kx, ky): samples i0, i1 of the w >= 0 half
-              const float2 s0 = my[swz(i0)], s1 = my[swz(i1)];
-              xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
-              xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
-              // mirror (-kx, -ky): conj of samples -i0, -i1 (mod N)
-              const float2 m0 = my[swz((N - i0) & (N - 1))], m1 = my[swz((N - i1) & (N - 1))];
-              xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
-              xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
-            }
-          }
-          if (ok) dst[kz] = xa;
-          if (ok2) dst2[kz] = xb;
+    const int ex = SP == SP_F16 ? *a.e_out : 0;
+    typename ST_::T* outp = static_cast<typename ST_::T*>(a.out);
+    // a rolled loop keeps the register footprint (and so the occupancy) of the remap low
+#pragma unroll 2
+    for (int kz = p; kz < a.nt; kz += P) {
+      float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
+      if (kz > 0 && kz < HALF) {
+        const double q2 = A + double(kz * kz);
+        const float qf = __builtin_amdgcn_sqrtf((float)q2);
+        const float rq = __builtin_amdgcn_rcpf(qf);
+        const double q0 = (double)qf;
+        const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
+        if (q <= double(HALF - 1)) {
+          const double fl = floor(q);
+          const int i0 = int(fl);
+          const int i1 = i0 + 1 < HALF ? i0 + 1 : HALF - 1;
+          const float fr = float(q - fl);
+          const float jac = float(kz) * rq * a.norm;
+          // column (kx, ky): samples i0, i1 of the w >= 0 half
+          const float2 s0 = my[swz(i0)], s1 = my[swz(i1)];
+          xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
+          xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
+          // mirror (-kx, -ky): conj of samples -i0, -i1 (mod N)
+          const float2 m0 = my[swz((N - i0) & (N - 1))], m1 = my[swz((N - i1) & (N - 1))];
+          xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
+          xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
         }
-      });
-    });
+      }
+      if constexpr (SP == SP_F16) {
+        xa = ldexp2(xa, ex);
+        xb = ldexp2(xb, ex);
+      }
+      if (ok) ST_::st(outp, dst + kz, xa);
+      if (ok2) ST_::st(outp, dst2 + kz, xb);
+    }
   }
+}
+
+// ---------------------------------------------------------------------------
+// FP16 storage scales (Section 4.2, data quantization: the input is scaled before the
+// forward transform and the spectrum before the inverse one)
+// ---------------------------------------------------------------------------
+//
+// Every forward intermediate is a partial DFT of g = tau t/(nt-1), so its magnitude is
+// at most B = sum |g|; the Stolt output is at most B/(Mx My Mt) (a lerp of spectrum
+// samples times Z/Z' <= 1 and the normalisation); each unnormalised inverse axis of
+// length M multiplies the bound by M.  With B = f 2^k (f in [0.5, 1)), storing the
+// forward intermediates times 2^(14-k) keeps them below 2^14 (binary16's largest
+// finite value is 65504) and the later ones follow by exact powers of two.  B is summed
+// in a fixed order, so the scales, and the result, are deterministic.
+
+__device__ __forceinline__ float block_sum_256(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void fk_l1_partial(const float2* __restrict__ tau, long long n2, int nt,
+                                                     float tscale, float* __restrict__ partials) {
+  __shared__ float red[4];
+  float acc = 0.f;
+  const long long stride = (long long)gridDim.x * 256;
+  auto term = [&](long long i, float2 v) {
+    const int t = (int)((2 * i) & (nt - 1));  // nt is an even power of two
+    return fabsf(v.x) * float(t) + fabsf(v.y) * float(t + 1);
+  };
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  // four loads in flight per thread
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    const float2 v0 = tau[i], v1 = tau[i + stride], v2 = tau[i + 2 * stride], v3 = tau[i + 3 * stride];
+    acc += (term(i, v0) + term(i + stride, v1)) + (term(i + 2 * stride, v2) + term(i + 3 * stride, v3));
+  }
+  for (; i < n2; i += stride) acc += term(i, tau[i]);
+  const float b = block_sum_256(acc * tscale, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(256) void fk_scale_exponents(const float* __restrict__ partials, int np,
+                                                          int* __restrict__ exps, int l_norm, int l_my,
+                                                          int l_mx) {
+  __shared__ float red[4];
+  float acc = 0.f;
+  for (int j = threadIdx.x; j < np; j += 256) acc += partials[j];
+  const float B = block_sum_256(acc, red);
+  if (threadIdx.x == 0) {
+    int k = 0;
+    if (B > 0.f && B <= 3.0e38f) frexpf(B, &k);
+    const int ef = (B > 0.f && B <= 3.0e38f) ? 14 - k : 0;
+    exps[0] = ef;                    // W1, W2: bound B
+    exps[1] = ef + l_norm;           // W3: bound B / (Mx My Mt)
+    exps[2] = exps[1] - l_my;        // W4: bound My B / (Mx My Mt)
+    exps[3] = exps[2] - l_mx;        // W5: bound Mx My B / (Mx My Mt)
+  }
+}
+
+hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
+                            int l_norm, int l_my, int l_mx, hipStream_t s) {
+  if (n % 2 != 0 || (nt & (nt - 1)) != 0 || nt < 2) return hipErrorInvalidValue;
+  const float tscale = (float)(1.0 / (double)(nt - 1));
+  hipLaunchKernelGGL(fk_l1_partial, dim3(kScaleBlocks), dim3(256), 0, s,
+                     reinterpret_cast<const float2*>(tau), n / 2, nt, tscale, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fk_scale_exponents, dim3(1), dim3(256), 0, s, partials, kScaleBlocks, exps, l_norm,
+                     l_my, l_mx);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -193,57 +294,71 @@ struct XTune {
   static constexpr int T = (N == 512) ? 16 : (N == 256 ? 32 : default_t(N));
 };
 
-template <int N>
+template <int N, int SP>
 static hipError_t launch_xr2c_n(const FkXArgs& a, int ny, const float2* tw, hipStream_t s) {
   constexpr int E = XTune<N>::E, T = XTune<N>::T;
   using C = StridedCfg<N, E, T>;
   dim3 grid((unsigned)((a.nt / 2 + T - 1) / T), (unsigned)ny);
-  hipLaunchKernelGGL((fk_xr2c<N, E, T>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((fk_xr2c<N, E, T, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s) {
+template <int SP>
+static hipError_t launch_xr2c_sp(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_xr2c_n<8>(a, ny, tw, s);
-    case 16: return launch_xr2c_n<16>(a, ny, tw, s);
-    case 32: return launch_xr2c_n<32>(a, ny, tw, s);
-    case 64: return launch_xr2c_n<64>(a, ny, tw, s);
-    case 128: return launch_xr2c_n<128>(a, ny, tw, s);
-    case 256: return launch_xr2c_n<256>(a, ny, tw, s);
-    case 512: return launch_xr2c_n<512>(a, ny, tw, s);
-    case 1024: return launch_xr2c_n<1024>(a, ny, tw, s);
-    case 2048: return launch_xr2c_n<2048>(a, ny, tw, s);
+    case 8: return launch_xr2c_n<8, SP>(a, ny, tw, s);
+    case 16: return launch_xr2c_n<16, SP>(a, ny, tw, s);
+    case 32: return launch_xr2c_n<32, SP>(a, ny, tw, s);
+    case 64: return launch_xr2c_n<64, SP>(a, ny, tw, s);
+    case 128: return launch_xr2c_n<128, SP>(a, ny, tw, s);
+    case 256: return launch_xr2c_n<256, SP>(a, ny, tw, s);
+    case 512: return launch_xr2c_n<512, SP>(a, ny, tw, s);
+    case 1024: return launch_xr2c_n<1024, SP>(a, ny, tw, s);
+    case 2048: return launch_xr2c_n<2048, SP>(a, ny, tw, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp) {
+  if (sp == SP_F16) return launch_xr2c_sp<SP_F16>(n, a, ny, tw, s);
+  if (sp == SP_BF16) return launch_xr2c_sp<SP_BF16>(n, a, ny, tw, s);
+  return launch_xr2c_sp<SP_F32>(n, a, ny, tw, s);
 }
 
 // column pass: 16 samples per thread (64 threads per column) from timing sweeps at
 // 1024-point columns; persistent blocks, a few per CU
 constexpr long long kColumnBlocks = 2048;
 
-template <int N>
+template <int N, int SP>
 static hipError_t launch_pair_n(const FkPairArgs& a, const float2* tw, hipStream_t s) {
   constexpr int E = (N >= 1024) ? 16 : default_e(N);
   using C = ContigCfg<N, E>;
   const long long groups = (a.nwork + C::L - 1) / C::L;
   dim3 grid((unsigned)(groups < kColumnBlocks ? groups : kColumnBlocks));
-  hipLaunchKernelGGL((fk_column_pair<N, E>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((fk_column_pair<N, E, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s) {
+template <int SP>
+static hipError_t launch_pair_sp(int n, const FkPairArgs& a, const float2* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_pair_n<8>(a, tw, s);
-    case 16: return launch_pair_n<16>(a, tw, s);
-    case 32: return launch_pair_n<32>(a, tw, s);
-    case 64: return launch_pair_n<64>(a, tw, s);
-    case 128: return launch_pair_n<128>(a, tw, s);
-    case 256: return launch_pair_n<256>(a, tw, s);
-    case 512: return launch_pair_n<512>(a, tw, s);
-    case 1024: return launch_pair_n<1024>(a, tw, s);
-    case 2048: return launch_pair_n<2048>(a, tw, s);
+    case 8: return launch_pair_n<8, SP>(a, tw, s);
+    case 16: return launch_pair_n<16, SP>(a, tw, s);
+    case 32: return launch_pair_n<32, SP>(a, tw, s);
+    case 64: return launch_pair_n<64, SP>(a, tw, s);
+    case 128: return launch_pair_n<128, SP>(a, tw, s);
+    case 256: return launch_pair_n<256, SP>(a, tw, s);
+    case 512: return launch_pair_n<512, SP>(a, tw, s);
+    case 1024: return launch_pair_n<1024, SP>(a, tw, s);
+    case 2048: return launch_pair_n<2048, SP>(a, tw, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s, int sp) {
+  if (sp == SP_F16) return launch_pair_sp<SP_F16>(n, a, tw, s);
+  if (sp == SP_BF16) return launch_pair_sp<SP_BF16>(n, a, tw, s);
+  return launch_pair_sp<SP_F32>(n, a, tw, s);
 }
 
 }  // namespace nlos

@@ -33,24 +33,44 @@ bool is_pow2_in(long long n, long long lo, long long hi) {
 
 // Elements between consecutive y (or ky) rows of the f-k intermediates: Mx * nt plus
 // 256 bytes, so that the y passes, which step through rows, do not hit the same
-// memory channels at a power-of-two stride.
-size_t fk_row_stride(size_t Mx, size_t nt) { return Mx * nt + 32; }
+// memory channels at a power-of-two stride.  es is the bytes per complex element.
+size_t fk_row_stride(size_t Mx, size_t nt, size_t es) { return Mx * nt + 256 / es; }
 
-// f-k workspace (complex elements): region A holds W1 [ny][Mx/2+1][nt] and W2
-// [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [ny][Mx][nt] (rs_full);
-// region B holds W3 [My][Mx][nt] (rs_full), later W5 [ny][nx][nt].
+// log2 of a power of two (0 for n <= 1)
+int ilog2(int n) {
+  int k = 0;
+  while ((1 << (k + 1)) <= n) ++k;
+  return k;
+}
+
+size_t fk_elem_bytes(nlos_precision p) { return p == NLOS_FP32 ? 8 : 4; }
+int fk_sp(nlos_precision p) { return p == NLOS_FP16 ? nlos::SP_F16 : p == NLOS_BF16 ? nlos::SP_BF16 : nlos::SP_F32; }
+
+// f-k workspace (complex elements of es bytes): region A holds W1 [ny][Mx/2+1][nt] and
+// W2 [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [ny][Mx][nt] (rs_full);
+// region B holds W3 [My][Mx][nt] (rs_full), later W5 [ny][nx][nt].  FP16 appends the
+// scale scratch: kScaleBlocks partial sums and the four storage exponents.
 struct FkLayout {
-  size_t rs_half, rs_full, w2_off, b_off, total;
+  size_t es, rs_half, rs_full, w2_off, b_off, total;  // elements
+  size_t scale_off;                                   // bytes (FP16 only)
+  size_t bytes;
 };
 FkLayout fk_layout(const nlos_fk_desc* d) {
   const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny, nt = d->nt, ny = d->ny;
-  FkLayout L;
-  L.rs_half = fk_row_stride(Mx / 2 + 1, nt);
-  L.rs_full = fk_row_stride(Mx, nt);
+  FkLayout L{};
+  L.es = fk_elem_bytes(d->prec);
+  L.rs_half = fk_row_stride(Mx / 2 + 1, nt, L.es);
+  L.rs_full = fk_row_stride(Mx, nt, L.es);
   L.w2_off = ny * L.rs_half;
   const size_t a = std::max((ny + My) * L.rs_half, ny * L.rs_full);
-  L.b_off = (a + 31) / 32 * 32;
+  const size_t align = 256 / L.es;
+  L.b_off = (a + align - 1) / align * align;
   L.total = L.b_off + My * L.rs_full;
+  L.bytes = L.total * L.es;
+  if (d->prec == NLOS_FP16) {
+    L.scale_off = (L.bytes + 255) / 256 * 256;
+    L.bytes = L.scale_off + 4 * nlos::kScaleBlocks + 256;
+  }
   return L;
 }
 
@@ -143,7 +163,7 @@ static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
 
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
-    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi"};
+    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale"};
 
 extern "C" {
 
@@ -258,6 +278,8 @@ nlos_status nlos_set_stream(nlos_ctx* ctx, void* hip_stream) {
 
 static nlos_status get_workspace(nlos_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, void** out) {
   if (d_ws) {
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
+      return fail(ctx, NLOS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (ws_bytes < need)
       return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     *out = d_ws;
@@ -348,8 +370,6 @@ nlos_status nlos_fk_check(const nlos_fk_desc* d) {
     return fail(nullptr, NLOS_ERR_UNSUPPORTED,
                 "fk: padded sizes %lld x %lld x %lld must be powers of two in [8, 2048]", p * d->ny,
                 p * d->nx, p * d->nt);
-  if (d->prec != NLOS_FP32)
-    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "fk: only FP32 storage is built");
   return NLOS_OK;
 }
 
@@ -357,7 +377,7 @@ nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
   nlos_status st = nlos_fk_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bytes is NULL");
-  *bytes = fk_layout(d).total * 8;
+  *bytes = fk_layout(d).bytes;
   return NLOS_OK;
 }
 
@@ -405,11 +425,20 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   if (st != NLOS_OK) return st;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const FkLayout L = fk_layout(&d);
-  float2* base = static_cast<float2*>(ws);
-  float2* W1 = base;               // [ny][Mx/2+1][nt] half spectrum after the x pass
-  float2* W2 = base + L.w2_off;    // [My][Mx/2+1][nt] half spectrum after the y pass
-  float2* W3 = base + L.b_off;     // [My][Mx][nt] after the column pass
-  float2* W4 = base;               // [ny][Mx][nt] after the y-IFFT (W1, W2 are dead by then)
+  const int sp = fk_sp(d.prec);
+  char* base = static_cast<char*>(ws);
+  void* W1 = base;                          // [ny][Mx/2+1][nt] half spectrum after the x pass
+  void* W2 = base + L.w2_off * L.es;        // [My][Mx/2+1][nt] half spectrum after the y pass
+  void* W3 = base + L.b_off * L.es;         // [My][Mx][nt] after the column pass
+  void* W4 = base;                          // [ny][Mx][nt] after the y-IFFT (W1, W2 are dead)
+  void* W5 = W3;                            // [ny][nx][nt] after the x-IFFT (W3 is dead)
+  // FP16 storage exponents: [0] W1 and W2, [1] W3, [2] W4, [3] W5
+  int* ex = nullptr;
+  float* partials = nullptr;
+  if (sp == nlos::SP_F16) {
+    partials = reinterpret_cast<float*>(base + L.scale_off);
+    ex = reinterpret_cast<int*>(base + L.scale_off + 4 * nlos::kScaleBlocks);
+  }
   const long long RH = (long long)L.rs_half, RF = (long long)L.rs_full;
   hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
@@ -418,17 +447,26 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
+  if (ex) {
+    // FP16: power-of-two storage scales from the bound sum |tau| t/(nt-1)
+    const int l_my = ilog2((int)My), l_mx = ilog2((int)Mx), l_norm = l_my + l_mx + ilog2(p->Mt);
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_SCALE, [&] {
+      return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, l_my, l_mx, s);
+    }));
+  }
   // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx, kx in [0, Mx/2]
   FkXArgs x{};
   x.tau = d_tau; x.out = W1; x.out_plane = RH; x.nx = (int)nx; x.nt = (int)nt;
   x.tscale = (float)(1.0 / (double)(nt - 1));
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s); }));
+  x.e_out = ex;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s, sp); }));
   // pass 2: y-FFT of the Mx/2 + 1 planes, zero padded to My
   StridedArgs a{};
   a.in = W1; a.out = W2;
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s); }));
+  a.e_in = ex; a.e_out = ex;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp); }));
   // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
   // column and its mirror; the remapped spectra (kz < nt) go to W3
   FkPairArgs c{};
@@ -436,26 +474,29 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   c.nwork = (Mx / 2 - 1) * My + 2 * (My / 2 + 1);
   c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s); }));
+  c.e_in = ex; c.e_out = ex ? ex + 1 : nullptr;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp); }));
   // pass 4: y-IFFT, keep y < ny
   a = StridedArgs{};
   a.in = W3; a.out = W4;
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
-  // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt] (over W3, which is dead)
-  float2* W5 = W3;
+  a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp); }));
+  // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
   a = StridedArgs{};
   a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
+  a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp); }));
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
   z.in = W5; z.out = d_vol; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
   z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = d_img;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s); }));
+  z.e_in = ex ? ex + 3 : nullptr;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp); }));
   return NLOS_OK;
 }
 

@@ -8,6 +8,9 @@
 
 namespace nlos {
 
+// storage precision of complex intermediates (float2, __half2, __hip_bfloat162)
+enum { SP_F32 = 0, SP_F16 = 1, SP_BF16 = 2 };
+
 // strided_fft load / store modes
 enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
 enum { ST_C64 = 0, ST_ABS2_IMG = 1, ST_ABS_IMG = 2 };
@@ -28,6 +31,10 @@ struct StridedArgs {
   float oscale;        // ST_ABS2_IMG: output = |v|^2 * oscale; ST_ABS_IMG: |v| * oscale
   float* img;          // ST_ABS*_IMG: img[plane * img_plane + n] = max over columns (may be null)
   long long img_plane;
+  // four-byte storage (SP_F16 / SP_BF16): an FP16 input holds value * 2^(*e_in) and an
+  // FP16 output is written as value * 2^(*e_out); BF16 is unscaled
+  const int* e_in;
+  const int* e_out;
 };
 
 // Lines along the contiguous axis: line `ln` is in[ln * in_line + n], n < n_in.
@@ -42,27 +49,31 @@ struct ContigArgs {
   long long img_lines;
   const int* bins;     // CS_BINS: out[ln * nbins + f] = X[bins[f]]
   int nbins;
+  const int* e_in;     // FP16 input: holds value * 2^(*e_in)
 };
 
 // f-k pass 1: tau[ny][nx][nt] (float) -> half spectrum out[ny][Mx/2 + 1][nt] with
 // plane (y) stride out_plane, two real t-columns per complex line.
 struct FkXArgs {
   const float* tau;
-  float2* out;
+  void* out;           // float2 or four-byte complex
   long long out_plane;
   int nx, nt;
   float tscale;        // 1 / (nt - 1)
+  const int* e_out;    // FP16 output: written as value * 2^(*e_out)
 };
 
 // f-k pass 3: input half spectrum in[ky][kx <= Mx/2][nt] (row stride in_row), output full
 // spectrum columns out[ky][kx][nt] (row stride out_row); nwork paired work items.
 struct FkPairArgs {
-  const float2* in;
-  float2* out;
+  const void* in;      // float2 or four-byte complex
+  void* out;
   long long in_row, out_row, nwork;
   int nt, Mx, My;
   double sxk, syk;     // Stolt coordinate per signed kx, ky in units of the t bins
   float norm;          // 1 / (Mx My Mt)
+  const int* e_in;     // FP16: input holds value * 2^(*e_in), output is written
+  const int* e_out;    // as value * 2^(*e_out)
 };
 
 // Radial propagation over chunks of pixels that share the lower radial bin.
@@ -82,11 +93,17 @@ struct RsdPropArgs {
 };
 
 hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
-                          const float2* tw, hipStream_t s);
+                          const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a,
-                         const float2* tw, hipStream_t s);
-hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s);
-hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s);
+                         const float2* tw, hipStream_t s, int sp = 0);
+hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp = 0);
+hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s, int sp = 0);
+// FP16 storage scales of the f-k intermediates from the bound B = sum |tau| t/(nt-1)
+// (nt a power of two): partials[kScaleBlocks] scratch, exps[4] = the exponents of
+// W1/W2, W3, W4, W5; l_norm = log2(Mx My Mt), l_my = log2 My, l_mx = log2 Mx.
+constexpr int kScaleBlocks = 1024;
+hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
+                            int l_norm, int l_my, int l_mx, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s);

@@ -170,7 +170,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 14
+NLOS_PASS_COUNT = 15
 
 
 def nlos_pass_name(p: int) -> str:

@@ -222,7 +222,8 @@ class Server:
 
 def rsd_precisions(precision: str) -> Tuple[str, str]:
     """(data, kernel) storage of an RSD request: the reduced-precision form stores the
-    radial kernel K_r in FP16 (accumulated in FP64, rounded once on store)."""
+    radial kernel K_r in FP16 (accumulated in FP64, rounded once on store).  An f-k
+    request's precision is the storage of its complex intermediates (fp32, fp16, bf16)."""
     return ("fp32", "fp32") if precision == "fp32" else ("fp32", "fp16")
 
 

@@ -45,14 +45,15 @@ def test_fk_validation():
     assert "pad" in nlos.nlos_last_error() or nlos.nlos_last_error() != ""
 
 
-def fk_ws_expected(ny, nx, nt, pad):
+def fk_ws_expected(ny, nx, nt, pad, es=8):
     """Half spectra W1 [ny][Mx/2+1][nt] + W2 [My][Mx/2+1][nt] (later W4 [ny][Mx][nt]) and
-    W3 [My][Mx][nt], complex64, rows padded by 32 elements."""
+    W3 [My][Mx][nt], es bytes per complex element, rows padded by 256 bytes."""
     Mx, My = pad * nx, pad * ny
-    rh, rf = (Mx // 2 + 1) * nt + 32, Mx * nt + 32
+    padn = 256 // es
+    rh, rf = (Mx // 2 + 1) * nt + padn, Mx * nt + padn
     a = max((ny + My) * rh, ny * rf)
-    a = (a + 31) // 32 * 32
-    return (a + My * rf) * 8
+    a = (a + padn - 1) // padn * padn
+    return (a + My * rf) * es
 
 
 def test_fk_workspace_is_exact():
@@ -63,6 +64,21 @@ def test_fk_workspace_is_exact():
     assert nlos.nlos_fk_workspace_bytes(d) == fk_ws_expected(16, 32, 64, 1)
     with pytest.raises(nlos.NlosError):
         nlos.nlos_fk_workspace_bytes(nlos.fk_desc(3, 8, 8, 1.0, 1.0, 32.0))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape", [(256, 256, 512, 2), (16, 32, 64, 1), (8, 8, 2048, 1)])
+def test_fk_reduced_workspace(prec, shape):
+    """Four-byte intermediates; FP16 adds 1024 partial sums and the four storage
+    exponents, 256-byte aligned."""
+    ny, nx, nt, pad = shape
+    d = nlos.fk_desc(nx, ny, nt, 1.0, 1.0, 32.0, pad=pad, prec=prec)
+    data = fk_ws_expected(ny, nx, nt, pad, es=4)
+    want = data if prec == "bf16" else (data + 255) // 256 * 256 + 4 * 1024 + 256
+    assert nlos.nlos_fk_workspace_bytes(d) == want
+    if shape[0] == 256:
+        full = nlos.nlos_fk_workspace_bytes(nlos.fk_desc(nx, ny, nt, 1.0, 1.0, 32.0, pad=pad))
+        assert nlos.nlos_fk_workspace_bytes(d) < 0.51 * full
 
 
 def test_bin_validation():
