@@ -147,6 +147,27 @@ def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=500
     }
 
 
+def copy_calibration(args):
+    """torch's device copy of 1 GiB (256 Mi float32): 1 GiB read + 1 GiB written per
+    launch; prints its bandwidth.  Under rocprofv3 --pmc its FETCH_SIZE and WRITE_SIZE
+    give the counter-to-bytes factor used for the other workloads."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "copy_GBps", "value": round(2 * 4 * n / sec / 1e9, 1), "unit": "GB/s",
+                      "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "steps": args.steps, "ms_per_step": round(sec * 1e3, 4)}), flush=True)
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -162,7 +183,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
-                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2"])
+                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "copy_1GiB"],
+                    help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
+                         "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="f-k storage precision of the complex intermediates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -185,6 +208,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     kind, cname = args.workload.split("_")
+    if kind == "copy":
+        copy_calibration(args)
+        return
     cfg = scenes.CONFIGS[cname]
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
@@ -265,8 +291,11 @@ def main():
     if os.path.exists(prof_path):
         try:
             from paper_2608_28183_amd import build as _b
-            rec = json.load(open(prof_path)).get(f"{args.workload}:{dom}")
-            if rec and rec.get("source_sha") == _b.source_sha():
+            prof = json.load(open(prof_path))
+            key = f"{args.workload}:{args.prec if kind == 'fk' else 'fp32'}:{dom}"
+            rec = prof.get("entries", {}).get(key)
+            # counters taken from other kernel code do not describe this one
+            if rec and prof.get("source_sha") == _b.source_sha():
                 traffic = rec["bytes_per_launch"]
         except Exception:
             traffic = None
