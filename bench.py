@@ -64,7 +64,7 @@ def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
         "rsd_x": c * ny * nx * nf + c * ny * Mx * nf,
         "rsd_y": c * ny * Mx * nf + c * My * Mx * nf,
         # spectra, kernel rows (read at least once), pixel chunks and the propagated planes
-        "rsd_propagate": c * My * Mx * nf + c * nrho * nf * nd + 52 * nchunks + c * My * Mx * nd,
+        "rsd_propagate": c * My * Mx * nf + c * nrho * nf * nd + (4 + 12 * 64) * nchunks + c * My * Mx * nd,
         "rsd_yi": c * My * Mx * nd + c * ny * Mx * nd,
         "rsd_xi": c * ny * Mx * nd + 4 * ny * nx * nd + 4 * ny * nx,
         "fill": 4 * ny * nx,

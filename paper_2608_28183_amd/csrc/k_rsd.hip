@@ -2,26 +2,27 @@
 // inner loop) for gfx950.
 //
 //   C[pix][d] = sum_f w_f P^[pix][f] a(pix) lerp(K_r[., f, d], rho~(pix))
-//             = sum_f (wa w_f P^) K_r[i0][f][d] + (wb w_f P^) K_r[i1][f][d]
+//             = sum_f (wa w_f P^) K_r[i0][f][d] + (wb w_f P^) K_r[i0+1][f][d]
 //
-// The pixels are pre-sorted by their lower radial bin i0 into chunks of up to 8 that
-// share i0 (plan data), so one wave64 handles a chunk with one depth per lane: the two
-// kernel rows K_r[i0][f][.], K_r[i1][f][.] are loaded once per frequency (512-byte
-// rows across the lanes) and applied to all 8 pixels, whose tap-weighted phasors are
-// staged in LDS and read as broadcasts.  Output rows C[pix][0..Nd) are written
-// contiguously.  Every C element is produced by one lane in a fixed frequency order.
+// The plan sorts the pixels by their lower radial bin i0 and groups them into chunks of
+// up to 64 that share i0.  One wave64 takes a chunk, one pixel per lane, and a slice of
+// kDepths depths: the two kernel rows K_r[i0][f][d0..d0+kDepths) and K_r[i0+1][f][...]
+// are the same for the whole wave, so they come in through the scalar unit and enter the
+// FMAs as scalar operands, and each kernel value is loaded once per 64 pixels.  The
+// lane's own phasor P^[pix][f] is read from its contiguous frequency row.  Every C
+// element is produced by one lane in a fixed frequency order.
 #include <hip/hip_fp16.h>
 
 #include "nlos_internal.hpp"
 
 namespace nlos {
 
-constexpr int kChunkPix = 8;    // pixels per chunk (matches the plan's chunking)
-constexpr int kFreqTile = 64;   // frequencies staged per LDS round
-constexpr int kWaves = 4;       // waves (chunks) per block
+constexpr int kGroupPix = 64;   // pixels per chunk (one per lane; matches the plan)
+constexpr int kDepths = 8;      // depths per wave
+constexpr int kWavesPerBlock = 4;
 
 template <bool FP16>
-__device__ __forceinline__ float2 load_kr(const void* kr, long long i) {
+__device__ __forceinline__ float2 load_kr(const void* __restrict__ kr, long long i) {
   if constexpr (FP16) {
     const __half2 h = static_cast<const __half2*>(kr)[i];
     return __half22float2(h);
@@ -30,81 +31,96 @@ __device__ __forceinline__ float2 load_kr(const void* kr, long long i) {
   }
 }
 
+// acc += pa K0 + pb K1 (complex), fixed operation order
+__device__ __forceinline__ void cmac2(float2& acc, float2 pa, float2 k0, float2 pb, float2 k1) {
+  acc.x = fmaf(pa.x, k0.x, fmaf(-pa.y, k0.y, fmaf(pb.x, k1.x, fmaf(-pb.y, k1.y, acc.x))));
+  acc.y = fmaf(pa.x, k0.y, fmaf(pa.y, k0.x, fmaf(pb.x, k1.y, fmaf(pb.y, k1.x, acc.y))));
+}
+
+// One frequency f of the lane's pixel: tap-weighted phasors, then the ND depths of the
+// wave's slice (kernel rows o0, o1 are wave-uniform).
+template <bool FP16, int ND>
+__device__ __forceinline__ void rsd_freq(float2* acc, float2 p, float2 wf, float wa, float wb, const void* kr,
+                                         long long o0, long long o1) {
+  const float2 pw = make_float2(p.x * wf.x - p.y * wf.y, p.x * wf.y + p.y * wf.x);
+  const float2 pa = make_float2(pw.x * wa, pw.y * wa);
+  const float2 pb = make_float2(pw.x * wb, pw.y * wb);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) cmac2(acc[j], pa, load_kr<FP16>(kr, o0 + j), pb, load_kr<FP16>(kr, o1 + j));
+}
+
 template <bool FP16>
 __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
-  // per wave: tap-weighted phasors pa[j][f], pb[j][f] of one frequency tile
-  __shared__ float2 sp[kWaves][2][kChunkPix][kFreqTile];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform work index: chunk g, depth slice starting at d0
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nds = (a.Nd + kDepths - 1) / kDepths;
+  const long long w = (long long)blockIdx.x * kWavesPerBlock + wib;
+  if (w >= a.nchunks * nds) return;
+  const long long g = w / nds;
+  const int d0 = (int)(w % nds) * kDepths;
   const int Nf = a.Nf, Nd = a.Nd;
-  const long long ngroups = (a.nchunks + kWaves - 1) / kWaves;
-  for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const long long c = g * kWaves + wave;
-    const bool cok = c < a.nchunks;
-    const int i0 = cok ? a.chunk_i0[c] : -1;
+  const int i0 = a.chunk_i0[g];
+  const int pix = a.chunk_pix[g * kGroupPix + lane];
+  float2 acc[kDepths];
+#pragma unroll
+  for (int j = 0; j < kDepths; ++j) acc[j] = make_float2(0.f, 0.f);
+  if (i0 >= 0) {
     const int i1 = i0 + 1 < a.cut_idx ? i0 + 1 : a.cut_idx;
-    int pix[kChunkPix];
-    float wa[kChunkPix], wb[kChunkPix];
+    // unused slots have wa = wb = 0 and read pixel 0's row
+    const float wa = a.chunk_wa[g * kGroupPix + lane];
+    const float wb = a.chunk_wb[g * kGroupPix + lane];
+    const float2* __restrict__ ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * Nf;
+    long long o0 = (long long)i0 * Nf * Nd + d0;
+    long long o1 = (long long)i1 * Nf * Nd + d0;
+    if (d0 + kDepths <= Nd) {
+      int f = 0;
+      // eight phasor loads in flight per lane
+      for (; f + 8 <= Nf; f += 8) {
+        float2 p[8];
 #pragma unroll
-    for (int j = 0; j < kChunkPix; ++j) {
-      pix[j] = cok ? a.chunk_pix[c * kChunkPix + j] : -1;
-      wa[j] = cok ? a.chunk_wa[c * kChunkPix + j] : 0.f;
-      wb[j] = cok ? a.chunk_wb[c * kChunkPix + j] : 0.f;
-    }
-    for (int d0 = 0; d0 < Nd; d0 += 64) {
-      const int d = d0 + lane;
-      const bool dok = d < Nd && i0 >= 0;
-      float2 acc[kChunkPix];
+        for (int u = 0; u < 8; ++u) p[u] = ph[f + u];
 #pragma unroll
-      for (int j = 0; j < kChunkPix; ++j) acc[j] = make_float2(0.f, 0.f);
-      for (int f0 = 0; f0 < Nf; f0 += kFreqTile) {
-        // stage pa = wa w_f P^[pix][f], pb = wb w_f P^[pix][f] for this tile
-        __syncthreads();
-        const int f = f0 + lane;
-        const bool fok = f < Nf && i0 >= 0;
-        const float2 wf = fok ? a.w[f] : make_float2(0.f, 0.f);
-#pragma unroll
-        for (int j = 0; j < kChunkPix; ++j) {
-          float2 ph = make_float2(0.f, 0.f);
-          if (fok && pix[j] >= 0) ph = a.Ph[(long long)pix[j] * Nf + f];
-          const float2 pw = make_float2(ph.x * wf.x - ph.y * wf.y, ph.x * wf.y + ph.y * wf.x);
-          sp[wave][0][j][lane] = make_float2(pw.x * wa[j], pw.y * wa[j]);
-          sp[wave][1][j][lane] = make_float2(pw.x * wb[j], pw.y * wb[j]);
-        }
-        __syncthreads();
-        if (i0 >= 0) {
-          const int nft = Nf - f0 < kFreqTile ? Nf - f0 : kFreqTile;
-          const long long r0 = ((long long)i0 * Nf + f0) * Nd + d;
-          const long long r1 = ((long long)i1 * Nf + f0) * Nd + d;
-          for (int ff = 0; ff < nft; ++ff) {
-            float2 k0 = make_float2(0.f, 0.f), k1 = make_float2(0.f, 0.f);
-            if (dok) {
-              k0 = load_kr<FP16>(a.Kr, r0 + (long long)ff * Nd);
-              k1 = load_kr<FP16>(a.Kr, r1 + (long long)ff * Nd);
-            }
-#pragma unroll
-            for (int j = 0; j < kChunkPix; ++j) {
-              const float2 pa = sp[wave][0][j][ff];
-              const float2 pb = sp[wave][1][j][ff];
-              acc[j].x = fmaf(pa.x, k0.x, fmaf(-pa.y, k0.y, fmaf(pb.x, k1.x, fmaf(-pb.y, k1.y, acc[j].x))));
-              acc[j].y = fmaf(pa.x, k0.y, fmaf(pa.y, k0.x, fmaf(pb.x, k1.y, fmaf(pb.y, k1.x, acc[j].y))));
-            }
-          }
+        for (int u = 0; u < 8; ++u) {
+          rsd_freq<FP16, kDepths>(acc, p[u], a.w[f + u], wa, wb, a.Kr, o0, o1);
+          o0 += Nd;
+          o1 += Nd;
         }
       }
-      if (d < Nd) {
+      for (; f < Nf; ++f) {
+        rsd_freq<FP16, kDepths>(acc, ph[f], a.w[f], wa, wb, a.Kr, o0, o1);
+        o0 += Nd;
+        o1 += Nd;
+      }
+    } else {
+      // last, partial depth slice
+      const int nd = Nd - d0;
+      for (int f = 0; f < Nf; ++f) {
+        const float2 p = ph[f], wf = a.w[f];
+        const float2 pw = make_float2(p.x * wf.x - p.y * wf.y, p.x * wf.y + p.y * wf.x);
+        const float2 pa = make_float2(pw.x * wa, pw.y * wa);
+        const float2 pb = make_float2(pw.x * wb, pw.y * wb);
 #pragma unroll
-        for (int j = 0; j < kChunkPix; ++j)
-          if (pix[j] >= 0) a.C[(long long)pix[j] * Nd + d] = acc[j];
+        for (int j = 0; j < kDepths; ++j)
+          if (j < nd) cmac2(acc[j], pa, load_kr<FP16>(a.Kr, o0 + j), pb, load_kr<FP16>(a.Kr, o1 + j));
+        o0 += Nd;
+        o1 += Nd;
       }
     }
   }
+  if (pix < 0) return;
+  float2* out = a.C + (long long)pix * Nd + d0;
+#pragma unroll
+  for (int j = 0; j < kDepths; ++j)
+    if (d0 + j < Nd) out[j] = acc[j];
 }
 
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
-  const long long groups = (a.nchunks + kWaves - 1) / kWaves;
-  const long long blocks = groups < 4096 ? groups : 4096;
+  const long long nds = (a.Nd + kDepths - 1) / kDepths;
+  const long long waves = a.nchunks * nds;
+  const long long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   if (a.kernel_fp16)
     hipLaunchKernelGGL(rsd_propagate<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   else

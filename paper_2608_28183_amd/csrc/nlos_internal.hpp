@@ -83,9 +83,9 @@ struct RsdPropArgs {
   const float2* w;         // [Nf] complex frequency weights
   float2* C;               // [npix][Nd] propagated spectra
   const int* chunk_i0;     // [nchunks] lower radial bin (-1: all-zero chunk)
-  const int* chunk_pix;    // [nchunks][8] pixel index or -1
-  const float* chunk_wa;   // [nchunks][8] a (1 - alpha)
-  const float* chunk_wb;   // [nchunks][8] a alpha
+  const int* chunk_pix;    // [nchunks][64] pixel index or -1
+  const float* chunk_wa;   // [nchunks][64] a (1 - alpha), 0 in unused slots
+  const float* chunk_wb;   // [nchunks][64] a alpha, 0 in unused slots
   long long nchunks;
   int Nf, Nd;
   int cut_idx;

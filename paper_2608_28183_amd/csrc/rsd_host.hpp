@@ -45,7 +45,7 @@ void rsd_radius_map(const RsdInputs& in, const RsdGeometry& g, std::vector<doubl
 // chunks of at most kChunk pixels with one i0; pixels with a = 0 form chunks with
 // i0 = -1 (their spectrum is zero).  Slot j of chunk c is pix[c * kChunk + j]
 // (-1 when unused).
-constexpr int kChunk = 8;
+constexpr int kChunk = 64;
 struct RsdChunks {
   std::vector<int> i0;
   std::vector<int> pix;
