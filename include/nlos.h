@@ -61,7 +61,8 @@ typedef struct nlos_rsd_plan nlos_rsd_plan;
 nlos_status nlos_create(int device, void *hip_stream, nlos_ctx **out);
 /* Frees the context's pool and tables (waits for its stream first).  NULL is a no-op. */
 nlos_status nlos_destroy(nlos_ctx *ctx);
-/* Later calls on ctx enqueue on hip_stream. */
+/* Waits for the work already enqueued on the current stream (the context's
+ * workspace pool is ordered by it), then later calls on ctx enqueue on hip_stream. */
 nlos_status nlos_set_stream(nlos_ctx *ctx, void *hip_stream);
 /* Static text for a status code. */
 const char *nlos_status_string(nlos_status s);

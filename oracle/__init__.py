@@ -15,6 +15,7 @@ Modules
   rsd      -- phasor DFT and radial RSD propagation (Section 4.3 Eq. 4-7,
               supplementary sampling rules, Algorithm 4) plus the exact dense
               and direct-sum RSD used as pins
+  moe      -- mixture of experts of the two (Section 4.4, Eq. 10)
   metrics  -- error measures (relative L2, PSNR, argmax distance)
 
 Every function states the passage it follows.  Readings of silent or garbled

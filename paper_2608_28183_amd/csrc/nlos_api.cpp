@@ -272,6 +272,9 @@ nlos_status nlos_destroy(nlos_ctx* ctx) {
 
 nlos_status nlos_set_stream(nlos_ctx* ctx, void* hip_stream) {
   if (!ctx) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_set_stream: ctx is NULL");
+  // the context's pool is ordered by its stream: drain the old one
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return NLOS_OK;
 }
