@@ -71,6 +71,24 @@ def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
     }
 
 
+def moe_pass_bytes(ny, nx, nt, pad, nf, nd, nrho):
+    """Algorithmic bytes of the mixture-of-experts passes: the f-k passes on the unscaled
+    transient (images only, no volume), the RSD phasors from the shared half spectrum,
+    the RSD propagation and inverse passes (image only) and the mixture."""
+    Mx, My = pad * nx, pad * ny
+    fk = fk_pass_bytes(ny, nx, nt, pad)
+    fk["fk_zi"] = 8 * ny * nx * nt + 4 * ny * nx
+    rsd = rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho)
+    out = {k: fk[k] for k in ("fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi", "fk_zi")}
+    out["moe_phasor"] = 8 * My * (Mx // 2 + 1) * nt + 8 * My * Mx * nf
+    out["rsd_propagate"] = rsd["rsd_propagate"]
+    out["rsd_yi"] = rsd["rsd_yi"]
+    out["rsd_xi"] = 8 * ny * Mx * nd + 4 * ny * nx
+    out["moe_mix"] = 4 * 4 * ny * nx
+    out["fill"] = 8 * ny * nx
+    return out
+
+
 def cpu_baseline_fk(cfg, fraction=2):
     """The FP64 oracle, untuned, on a bounded sample of the f-k workload: each oracle
     step runs on 1/fraction of its independent slices of the full-size padded volume
@@ -183,7 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
-                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "copy_1GiB"],
+                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "moe_c4", "moe_c3",
+                             "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -252,6 +271,39 @@ def main():
                                 f"{len(p.freq_bins)} freqs, {p.n_depth} depths",
                     "shape": [ny, nx, nt], "pad": cfg.pad, "n_freq": len(p.freq_bins),
                     "n_depth": p.n_depth}
+    elif kind == "moe":
+        tau = torch.from_numpy(scenes.config_transient(cname)).to(dev)
+        p = scenes.rsd_params(cfg)
+        plan = runtime.MoePlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad,
+                               p.freq_bins, p.weights, p.n_depth, p.depth0, p.depth_step)
+        ws = plan.workspace()
+        img = torch.empty((ny, nx), device=dev)
+        step = lambda: plan(tau, img, None, None, ws)  # noqa: E731
+        g = nlos.nlos_rsd_geometry_get(plan.rsd_desc)
+        nf = len(p.freq_bins)
+        pass_bytes = moe_pass_bytes(ny, nx, nt, cfg.pad, nf, p.n_depth, g["n_rho"])
+        metric, unit = "moe_images_per_s", "images/s"
+        units_per_step = 1
+        workload = {"workload": f"mixture of experts f-k x RSD (Eq. 10, beta 0.3) on {ny}x{nx}x{nt} "
+                                f"padded x{cfg.pad}, RSD {nf} freqs x {p.n_depth} depths",
+                    "shape": [ny, nx, nt], "pad": cfg.pad, "n_freq": nf, "n_depth": p.n_depth}
+        # the same two reconstructions run separately, for comparison
+        fkp = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad)
+        rsp = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
+                              p.weights, p.n_depth, p.depth0, p.depth_step)
+        ws2 = torch.empty(max(fkp.ws_bytes, rsp.ws_bytes), dtype=torch.uint8, device=dev)
+        im2 = torch.empty((ny, nx), device=dev)
+
+        def separate():
+            fkp(tau, None, im2, ws2)
+            rsp(tau, None, im2, ws2)
+
+        sqp = runtime.MoePlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad,
+                              p.freq_bins, p.weights, p.n_depth, p.depth0, p.depth_step,
+                              shared_spectrum=False)
+
+        def sequential():
+            sqp(tau, im2, None, None, ws)
     else:  # bin
         ev = scenes.config_events(cname, "shuffled")
         d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)
@@ -325,6 +377,22 @@ def main():
         print("[bench] serving run", file=sys.stderr, flush=True)
         serving = serve_bench()
 
+    moe_cmp = None
+    if kind == "moe":
+        def clock(fn):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / args.steps
+        sep, sq = clock(separate), clock(sequential)
+        moe_cmp = {"moe_shared_spectrum_ms": round(sec * 1e3, 4),
+                   "moe_branches_in_sequence_ms": round(sq * 1e3, 4),
+                   "separate_fk_then_rsd_ms": round(sep * 1e3, 4), "speedup_vs_separate": round(sep / sec, 3)}
+
     line = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
@@ -333,6 +401,7 @@ def main():
         "config": workload, "roofline": roofline, "cpu_baseline": cpu,
         "passes_ms": {k: round(v, 4) for k, v in avg_ms.items()},
         "serving": serving,
+        "moe_vs_separate": moe_cmp,
         "step_frac_of_hbm": round(total_alg * value / units_per_step / (HBM_PEAK_GBS * 1e9), 4),
         "step_bytes": total_alg,
     }

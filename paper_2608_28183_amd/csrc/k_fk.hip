@@ -37,7 +37,8 @@ __global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c(FkXArg
   const long long y = blockIdx.y;
   const int cc = blockIdx.x * T + c;        // complex line = real t-columns 2cc, 2cc+1
   const bool colok = 2 * cc < a.nt;
-  const float s0 = float(2 * cc) * a.tscale, s1 = float(2 * cc + 1) * a.tscale;
+  const float s0 = a.unscaled ? 1.f : float(2 * cc) * a.tscale;
+  const float s1 = a.unscaled ? 1.f : float(2 * cc + 1) * a.tscale;
 
   float2 v[S::E];
   static_for<S::E / S::R0>([&](auto b_) {
@@ -156,6 +157,10 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
         v[j] = ST_::cvt(raw[j]);
         if constexpr (SP == SP_F16) v[j] = ldexp2(v[j], e);
       }
+      if (a.tscale_in != 0.f) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = cscale(v[j], float(p + j * P) * a.tscale_in);
+      }
     }
     __syncthreads();  // the previous item's last LDS reads are done
     fft_run<S, false, true>(v, p, my, idx, tw, [&](int n, float2 val) { my[swz(n)] = val; });
@@ -208,6 +213,130 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
       if (ok2) ST_::st(outp, dst2 + kz, xb);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// mixture of experts (Section 4.4): RSD phasors from the shared spatial spectrum
+// ---------------------------------------------------------------------------
+//
+// The spatial DFT and the temporal DFT commute, so the RSD branch can take its phasors
+// P^[ky][kx][f] from the spatial spectrum T[ky][kx][t] of the transient that the f-k
+// branch also reads: one nt-point DFT per column at the selected bins.  The transient is
+// real, so T(-kx, -ky, t) = conj T(kx, ky, t) and the mirror column's phasors are
+// conj X[nt - k_f] of the same transform; only the kx <= Mx/2 half is stored.
+
+template <int N>
+__global__ __launch_bounds__((ContigCfg<N>::THREADS)) void moe_phasor_pair(MoePhasorArgs a,
+                                                                          const float2* __restrict__ tw) {
+  using C = ContigCfg<N>;
+  using S = typename C::S;
+  constexpr int E = S::E, P = C::P;
+  __shared__ float2 lds[C::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int l = tid / P;
+  const int p = tid % P;
+  float2* my = lds + l * C::LSTRIDE;
+  auto idx = [&](int n) { return swz(n); };
+  const long long w = (long long)blockIdx.x * C::L + l;
+  const bool ok = w < a.nwork;
+  const PairItem it = pair_item(ok ? w : 0, a.Mx, a.My);
+  const float2* src = a.in + (long long)it.ky * a.in_row + (long long)it.kx * a.nt;
+  float2 v[E];
+  static_for<E>([&](auto r_) {
+    constexpr int r = decltype(r_)::value;
+    v[r] = src[p + r * P];  // the column has exactly N = nt samples
+  });
+  fft_run<S, false, true>(v, p, my, idx, tw, [&](int n, float2 val) { my[swz(n)] = val; });
+  __syncthreads();
+  if (!ok) return;
+  float2* o1 = a.out + ((long long)it.ky * a.Mx + it.kx) * a.nbins;
+  float2* o2 = a.out + ((long long)it.ky2 * a.Mx + it.kx2) * a.nbins;
+  for (int f = p; f < a.nbins; f += P) {
+    const int k = a.bins[f];
+    o1[f] = my[swz(k)];
+    if (it.has_mirror) {
+      const float2 m = my[swz((N - k) & (N - 1))];
+      o2[f] = make_float2(m.x, -m.y);
+    }
+  }
+}
+
+hipError_t launch_moe_phasor_pair(const MoePhasorArgs& a, const float2* tw, hipStream_t s) {
+  auto go = [&](auto n_) -> hipError_t {
+    constexpr int N = decltype(n_)::value;
+    using C = ContigCfg<N>;
+    const long long blocks = (a.nwork + C::L - 1) / C::L;
+    hipLaunchKernelGGL((moe_phasor_pair<N>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a, tw);
+    return hipGetLastError();
+  };
+  switch (a.nt) {
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 16: return go(std::integral_constant<int, 16>{});
+    case 32: return go(std::integral_constant<int, 32>{});
+    case 64: return go(std::integral_constant<int, 64>{});
+    case 128: return go(std::integral_constant<int, 128>{});
+    case 256: return go(std::integral_constant<int, 256>{});
+    case 512: return go(std::integral_constant<int, 512>{});
+    case 1024: return go(std::integral_constant<int, 1024>{});
+    case 2048: return go(std::integral_constant<int, 2048>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Eq. 10 on the two branch images in three grid passes: the two maxima, the mixture and
+// its maximum, the normalisation.  Maxima of non-negative floats are taken with integer
+// atomic max on their bit patterns, which is order independent, so the result is
+// deterministic.  mx[0..2] (max F, max R, max m) must be zero on entry.
+__global__ __launch_bounds__(256) void moe_maxima(const float* __restrict__ fk_img, const float* __restrict__ rsd_img,
+                                                  int n, unsigned int* __restrict__ mx) {
+  float mf = 0.f, mr = 0.f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    mf = fmaxf(mf, fk_img[i]);
+    mr = fmaxf(mr, rsd_img[i]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mf = fmaxf(mf, __shfl_xor(mf, off, 64));
+    mr = fmaxf(mr, __shfl_xor(mr, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(mx, __float_as_uint(mf));
+    atomicMax(mx + 1, __float_as_uint(mr));
+  }
+}
+
+__global__ __launch_bounds__(256) void moe_product(const float* __restrict__ fk_img, const float* __restrict__ rsd_img,
+                                                   float* __restrict__ img, int n, float beta, float eps,
+                                                   unsigned int* __restrict__ mx) {
+  const float mf = __uint_as_float(mx[0]), mr = __uint_as_float(mx[1]);
+  const float sf = mf > 0.f ? 1.f / mf : 0.f, sr = mr > 0.f ? 1.f / mr : 0.f;
+  float mm = 0.f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float m = fk_img[i] * sf * powf(rsd_img[i] * sr + eps, beta);
+    img[i] = m;
+    mm = fmaxf(mm, m);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mm = fmaxf(mm, __shfl_xor(mm, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(mx + 2, __float_as_uint(mm));
+}
+
+__global__ __launch_bounds__(256) void moe_normalise(float* __restrict__ img, int n, const unsigned int* __restrict__ mx) {
+  const float mm = __uint_as_float(mx[2]);
+  const float sm = mm > 0.f ? 1.f / mm : 0.f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) img[i] *= sm;
+}
+
+hipError_t launch_moe_mix(const float* fk_img, const float* rsd_img, float* img, int n, float beta, float eps,
+                          unsigned int* mx, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = launch_fill_u32(mx, 3, 0u, s);
+  if (e != hipSuccess) return e;
+  const int blocks = std::min(256, (n + 255) / 256);
+  hipLaunchKernelGGL(moe_maxima, dim3(blocks), dim3(256), 0, s, fk_img, rsd_img, n, mx);
+  hipLaunchKernelGGL(moe_product, dim3(blocks), dim3(256), 0, s, fk_img, rsd_img, img, n, beta, eps, mx);
+  hipLaunchKernelGGL(moe_normalise, dim3(blocks), dim3(256), 0, s, img, n, mx);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

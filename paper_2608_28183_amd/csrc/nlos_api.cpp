@@ -91,6 +91,8 @@ struct nlos_ctx {
   bool timing = false;
   std::vector<TimedLaunch> recs;      // launches recorded since the last read
   std::vector<hipEvent_t> spare;      // recycled events
+  hipStream_t aux = nullptr;          // second stream of the mixture of experts
+  hipEvent_t fork[3] = {nullptr, nullptr, nullptr};
 };
 
 struct nlos_fk_plan {
@@ -137,7 +139,15 @@ static nlos_status fail(nlos_ctx* ctx, nlos_status s, const char* fmt, ...) {
 
 // Runs launch() and, when timing is on, brackets it with events on the stream.
 template <class F>
+static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch);
+template <class F>
 static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
+  return timed_on(ctx, ctx->stream, pass, launch);
+}
+
+// Runs launch() and, when timing is on, brackets it with events on `stream`.
+template <class F>
+static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch) {
   if (!ctx->timing) return launch();
   hipEvent_t ev[2];
   for (auto& e : ev) {
@@ -149,9 +159,9 @@ static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
       if (r != hipSuccess) return r;
     }
   }
-  hipError_t r = hipEventRecord(ev[0], ctx->stream);
+  hipError_t r = hipEventRecord(ev[0], stream);
   if (r == hipSuccess) r = launch();
-  if (r == hipSuccess) r = hipEventRecord(ev[1], ctx->stream);
+  if (r == hipSuccess) r = hipEventRecord(ev[1], stream);
   if (r != hipSuccess) {
     ctx->spare.push_back(ev[0]);
     ctx->spare.push_back(ev[1]);
@@ -163,7 +173,8 @@ static hipError_t timed(nlos_ctx* ctx, int pass, F launch) {
 
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
-    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale"};
+    "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale",
+    "moe_phasor", "moe_mix"};
 
 extern "C" {
 
@@ -266,6 +277,12 @@ nlos_status nlos_destroy(nlos_ctx* ctx) {
     (void)hipEventDestroy(t.stop);
   }
   for (auto& e : ctx->spare) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  for (auto& e : ctx->fork)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return NLOS_OK;
 }
@@ -275,6 +292,7 @@ nlos_status nlos_set_stream(nlos_ctx* ctx, void* hip_stream) {
   // the context's pool is ordered by its stream: drain the old one
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->aux) HIP_TRY(ctx, hipStreamSynchronize(ctx->aux));
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return NLOS_OK;
 }
@@ -410,22 +428,10 @@ nlos_status nlos_fk_plan_destroy(nlos_fk_plan* p) {
   return NLOS_OK;
 }
 
-nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_vol, float* d_img,
-                    void* d_ws, size_t ws_bytes) {
-  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: ctx or plan is NULL");
-  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau is NULL");
-  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
-    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau must be 8-byte aligned");
-  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_vol and d_img are both NULL");
-  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: plan of another device");
+// The f-k pass sequence on stream s with workspace ws (validated by the caller).
+static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, const float* d_tau, float* d_vol,
+                          float* d_img, void* ws) {
   const nlos_fk_desc& d = p->d;
-  size_t need = 0;
-  nlos_status st = nlos_fk_workspace_bytes(&d, &need);
-  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  void* ws = nullptr;
-  st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
-  if (st != NLOS_OK) return st;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const FkLayout L = fk_layout(&d);
   const int sp = fk_sp(d.prec);
@@ -443,17 +449,16 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
     ex = reinterpret_cast<int*>(base + L.scale_off + 4 * nlos::kScaleBlocks);
   }
   const long long RH = (long long)L.rs_half, RF = (long long)L.rs_full;
-  hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
   if (d_img)
-    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
   if (ex) {
     // FP16: power-of-two storage scales from the bound sum |tau| t/(nt-1)
     const int l_my = ilog2((int)My), l_mx = ilog2((int)Mx), l_norm = l_my + l_mx + ilog2(p->Mt);
-    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_SCALE, [&] {
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_SCALE, [&] {
       return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, l_my, l_mx, s);
     }));
   }
@@ -462,14 +467,14 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   x.tau = d_tau; x.out = W1; x.out_plane = RH; x.nx = (int)nx; x.nt = (int)nt;
   x.tscale = (float)(1.0 / (double)(nt - 1));
   x.e_out = ex;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s, sp); }));
   // pass 2: y-FFT of the Mx/2 + 1 planes, zero padded to My
   StridedArgs a{};
   a.in = W1; a.out = W2;
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
   a.e_in = ex; a.e_out = ex;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp); }));
   // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
   // column and its mirror; the remapped spectra (kz < nt) go to W3
   FkPairArgs c{};
@@ -478,29 +483,48 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
   c.e_in = ex; c.e_out = ex ? ex + 1 : nullptr;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp); }));
   // pass 4: y-IFFT, keep y < ny
   a = StridedArgs{};
   a.in = W3; a.out = W4;
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp); }));
   // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
   a = StridedArgs{};
   a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp); }));
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
   z.in = W5; z.out = d_vol; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
   z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = d_img;
   z.e_in = ex ? ex + 3 : nullptr;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp); }));
   return NLOS_OK;
+}
+
+nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_vol, float* d_img,
+                    void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: ctx or plan is NULL");
+  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau is NULL");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_tau must be 8-byte aligned");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: plan of another device");
+  const nlos_fk_desc& d = p->d;
+  size_t need = 0;
+  nlos_status st = nlos_fk_workspace_bytes(&d, &need);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
+  if (st != NLOS_OK) return st;
+  return fk_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -690,30 +714,22 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
   return NLOS_OK;
 }
 
-nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, float* d_vol, float* d_img,
-                     void* d_ws, size_t ws_bytes) {
-  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: ctx or plan is NULL");
-  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_tau is NULL");
-  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_vol and d_img are both NULL");
-  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: plan of another device");
+// The RSD pass sequence on stream s with workspace ws (validated by the caller).
+static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s, const float* d_tau, float* d_vol,
+                           float* d_img, void* ws) {
   const nlos_rsd_desc& d = p->d;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const long long Nf = d.n_freq, Nd = d.n_depth;
   const RsdLayout L = rsd_layout(&d);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
-  if (st != NLOS_OK) return st;
   float2* base = static_cast<float2*>(ws);
   float2* P = base;                 // [ny][nx][Nf]
   float2* X = base + L.b_off;       // [ny][Mx][Nf]
   float2* Ph = base + L.e_off;      // [My][Mx][Nf]
   float2* C = base + L.b_off;       // [My][Mx][Nd]
   float2* D = base;                 // [ny][Mx][Nd]
-  hipStream_t s = ctx->stream;
   const float2* tw = ctx->d_tw;
   if (d_img)
-    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
@@ -721,35 +737,254 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
   ContigArgs c{};
   c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
   c.bins = p->d_bins; c.nbins = (int)Nf;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
   // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
   a.in = P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
   a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
   // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
   a = StridedArgs{};
   a.in = X; a.out = Ph; a.in_plane = Nf; a.in_line = Mx * Nf; a.out_plane = Nf; a.out_line = Mx * Nf;
   a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
   // 4. radial propagation over pixel chunks: P^ -> C[pix][d]
   nlos::RsdPropArgs r{};
   r.Ph = Ph; r.Kr = p->d_kr; r.w = p->d_w; r.C = C;
   r.chunk_i0 = p->d_chunk_i0; r.chunk_pix = p->d_chunk_pix; r.chunk_wa = p->d_chunk_wa;
   r.chunk_wb = p->d_chunk_wb; r.nchunks = p->nchunks;
   r.Nf = (int)Nf; r.Nd = (int)Nd; r.cut_idx = p->g.cut_idx; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
   // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d]
   a = StridedArgs{};
   a.in = C; a.out = D; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;
   a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
   // 6. x-IFFT, keep x < nx, |I| / (Mx My) -> vol[y][x][d], max over depth -> img
   a = StridedArgs{};
   a.in = D; a.out = d_vol; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
   a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s); }));
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, float* d_vol, float* d_img,
+                     void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: ctx or plan is NULL");
+  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_tau is NULL");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: plan of another device");
+  const RsdLayout L = rsd_layout(&p->d);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
+  if (st != NLOS_OK) return st;
+  return rsd_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ws);
+}
+
+// ---------------------------------------------------------------------------
+// mixture of experts (Section 4.4, Eq. 10)
+// ---------------------------------------------------------------------------
+
+struct nlos_moe_plan {
+  nlos_fk_plan* fk = nullptr;
+  nlos_rsd_plan* rsd = nullptr;
+  float beta = 0.3f, eps = 1e-6f;
+  int shared = 0;  // 1: both branches read one shared spatial spectrum
+  int device = 0;
+};
+
+static bool close_rel(double a, double b) { return std::fabs(a - b) <= 1e-9 * std::max(std::fabs(a), std::fabs(b)); }
+
+nlos_status nlos_moe_check(const nlos_fk_desc* fk, const nlos_rsd_desc* rsd, double beta, double eps) {
+  nlos_status st = nlos_fk_check(fk);
+  if (st != NLOS_OK) return st;
+  st = nlos_rsd_check(rsd);
+  if (st != NLOS_OK) return st;
+  if (fk->nx != rsd->nx || fk->ny != rsd->ny || fk->nt != rsd->nt || fk->pad != rsd->pad ||
+      !close_rel(fk->bin_ps, rsd->bin_ps) || !close_rel(fk->wall_w_m / fk->nx, rsd->dx_m) ||
+      !close_rel(fk->wall_h_m / fk->ny, rsd->dy_m))
+    return fail(nullptr, NLOS_ERR_INVALID_ARG,
+                "moe: the f-k and RSD descriptors must describe the same transient and grid");
+  if (fk->prec != NLOS_FP32 || rsd->data_prec != NLOS_FP32)
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "moe: FP32 intermediates only");
+  if (!(beta >= 0.0) || !std::isfinite(beta) || !(eps > 0.0) || !std::isfinite(eps))
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "moe: need beta >= 0 and eps > 0, finite");
+  return NLOS_OK;
+}
+
+// MoE workspace: the f-k workspace (its W2 is the shared spatial spectrum), the RSD
+// workspace (P^, C, D) and the two branch images.
+struct MoeLayout {
+  size_t rsd_off, img_off, bytes;
+};
+static MoeLayout moe_layout(const nlos_fk_desc* fk, const nlos_rsd_desc* rsd) {
+  MoeLayout L;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  L.rsd_off = up(fk_layout(fk).bytes);
+  L.img_off = L.rsd_off + up(rsd_layout(rsd).total * 8);
+  L.bytes = L.img_off + up(2 * sizeof(float) * (size_t)fk->nx * fk->ny) + 256;  // + 3 maxima
+  return L;
+}
+
+nlos_status nlos_moe_workspace_bytes(const nlos_fk_desc* fk, const nlos_rsd_desc* rsd, size_t* bytes) {
+  nlos_status st = nlos_moe_check(fk, rsd, 0.3, 1e-6);
+  if (st != NLOS_OK) return st;
+  if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "moe: bytes is NULL");
+  *bytes = moe_layout(fk, rsd).bytes;
+  return NLOS_OK;
+}
+
+nlos_status nlos_moe_plan_create(nlos_ctx* ctx, const nlos_fk_desc* fk, const nlos_rsd_desc* rsd, double beta,
+                                 double eps, int shared_spectrum, nlos_moe_plan** out) {
+  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "moe_plan_create: NULL argument");
+  nlos_status st = nlos_moe_check(fk, rsd, beta, eps);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  nlos_moe_plan* p = new (std::nothrow) nlos_moe_plan();
+  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "moe_plan_create: host allocation");
+  p->device = ctx->device;
+  p->beta = (float)beta;
+  p->eps = (float)eps;
+  p->shared = shared_spectrum ? 1 : 0;
+  st = nlos_fk_plan_create(ctx, fk, &p->fk);
+  if (st == NLOS_OK) st = nlos_rsd_plan_create(ctx, rsd, &p->rsd);
+  if (st != NLOS_OK) {
+    nlos_fk_plan_destroy(p->fk);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_moe_plan_destroy(nlos_moe_plan* p) {
+  if (!p) return NLOS_OK;
+  nlos_fk_plan_destroy(p->fk);
+  nlos_rsd_plan_destroy(p->rsd);
+  delete p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_moe(nlos_ctx* ctx, const nlos_moe_plan* p, const float* d_tau, float* d_img, float* d_img_fk,
+                     float* d_img_rsd, void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_moe: ctx or plan is NULL");
+  if (!d_tau || !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_moe: d_tau and d_img are required");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_moe: d_tau must be 8-byte aligned");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_moe: plan of another device");
+  const nlos_fk_desc& fd = p->fk->d;
+  const nlos_rsd_desc& rd = p->rsd->d;
+  const MoeLayout ML = moe_layout(&fd, &rd);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, ML.bytes, &ws);
+  if (st != NLOS_OK) return st;
+  const long long nx = fd.nx, ny = fd.ny, nt = fd.nt, Mx = p->fk->Mx, My = p->fk->My;
+  const long long Nf = rd.n_freq, Nd = rd.n_depth;
+  const FkLayout L = fk_layout(&fd);
+  const RsdLayout R = rsd_layout(&rd);
+  char* base = static_cast<char*>(ws);
+  float2* W1 = reinterpret_cast<float2*>(base);
+  float2* W2 = W1 + L.w2_off;          // shared spatial half spectrum [My][Mx/2+1][nt]
+  float2* W3 = W1 + L.b_off;
+  float2* W4 = W1;
+  float2* W5 = W3;
+  float2* rbase = reinterpret_cast<float2*>(base + ML.rsd_off);
+  float2* Ph = rbase + R.e_off;        // [My][Mx][Nf]
+  float2* Cr = rbase + R.b_off;        // [My][Mx][Nd]
+  float2* Dr = rbase;                  // [ny][Mx][Nd]
+  float* scratch = reinterpret_cast<float*>(base + ML.img_off);  // two images
+  unsigned int* mx = reinterpret_cast<unsigned int*>(base + ML.bytes - 256);
+  float* img_fk = d_img_fk ? d_img_fk : scratch;
+  float* img_rsd = d_img_rsd ? d_img_rsd : scratch + nx * ny;
+  const long long RH = (long long)L.rs_half, RF = (long long)L.rs_full;
+  hipStream_t s0 = ctx->stream, s1 = ctx->aux;
+  const float2* tw = ctx->d_tw;
+  if (!p->shared) {
+    // the two complete reconstructions one after the other on the context stream (each
+    // fills the device by itself: overlapping the independent branches on two streams
+    // measured slower than this order)
+    nlos_status st1 = rsd_run(ctx, p->rsd, s0, d_tau, nullptr, img_rsd, base + ML.rsd_off);
+    if (st1 != NLOS_OK) return st1;
+    st1 = fk_run(ctx, p->fk, s0, d_tau, nullptr, img_fk, base);
+    if (st1 != NLOS_OK) return st1;
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_MOE_MIX, [&] {
+      return nlos::launch_moe_mix(img_fk, img_rsd, d_img, (int)(nx * ny), p->beta, p->eps, mx, s0);
+    }));
+    return NLOS_OK;
+  }
+  if (!ctx->aux) {
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));  // default priority
+    for (auto& e : ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    s1 = ctx->aux;
+  }
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+    hipError_t e = nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(img_fk), (size_t)nx * ny, 0u, s0);
+    return e != hipSuccess ? e : nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(img_rsd), (size_t)nx * ny, 0u, s0);
+  }));
+  // shared: x and y FFTs of the (unscaled) transient -> W2
+  FkXArgs x{};
+  x.tau = d_tau; x.out = W1; x.out_plane = RH; x.nx = (int)nx; x.nt = (int)nt;
+  x.tscale = (float)(1.0 / (double)(nt - 1)); x.unscaled = 1;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s0); }));
+  StridedArgs a{};
+  a.in = W1; a.out = W2;
+  a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
+  a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s0); }));
+  // fork: the RSD branch on the second stream
+  HIP_TRY(ctx, hipEventRecord(ctx->fork[0], s0));
+  HIP_TRY(ctx, hipStreamWaitEvent(s1, ctx->fork[0], 0));
+  const long long nwork = (Mx / 2 - 1) * My + 2 * (My / 2 + 1);
+  nlos::MoePhasorArgs ph{};
+  ph.in = W2; ph.out = Ph; ph.in_row = RH; ph.nwork = nwork; ph.nt = (int)nt; ph.Mx = (int)Mx; ph.My = (int)My;
+  ph.nbins = (int)Nf; ph.bins = p->rsd->d_bins;
+  HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_MOE_PHASOR, [&] { return nlos::launch_moe_phasor_pair(ph, tw, s1); }));
+  HIP_TRY(ctx, hipEventRecord(ctx->fork[1], s1));  // W2 no longer read by the RSD branch
+  nlos::RsdPropArgs r{};
+  r.Ph = Ph; r.Kr = p->rsd->d_kr; r.w = p->rsd->d_w; r.C = Cr;
+  r.chunk_i0 = p->rsd->d_chunk_i0; r.chunk_pix = p->rsd->d_chunk_pix; r.chunk_wa = p->rsd->d_chunk_wa;
+  r.chunk_wb = p->rsd->d_chunk_wb; r.nchunks = p->rsd->nchunks;
+  r.Nf = (int)Nf; r.Nd = (int)Nd; r.cut_idx = p->rsd->g.cut_idx; r.kernel_fp16 = rd.kernel_prec == NLOS_FP16;
+  HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s1); }));
+  a = StridedArgs{};
+  a.in = Cr; a.out = Dr; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;
+  a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
+  HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s1); }));
+  a = StridedArgs{};
+  a.in = Dr; a.out = nullptr; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
+  a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
+  a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = img_rsd; a.img_plane = nx;
+  HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s1); }));
+  HIP_TRY(ctx, hipEventRecord(ctx->fork[2], s1));
+  // f-k branch on the context stream: the t/(nt-1) scaling is applied as the columns load
+  FkPairArgs c{};
+  c.in = W2; c.out = W3; c.in_row = RH; c.out_row = RF; c.nwork = nwork;
+  c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
+  c.sxk = p->fk->sxk; c.syk = p->fk->syk; c.norm = p->fk->norm;
+  c.tscale_in = (float)(1.0 / (double)(nt - 1));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->fk->Mt, c, tw, s0); }));
+  HIP_TRY(ctx, hipStreamWaitEvent(s0, ctx->fork[1], 0));  // W4 overwrites W2
+  a = StridedArgs{};
+  a.in = W3; a.out = W4;
+  a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
+  a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s0); }));
+  a = StridedArgs{};
+  a.in = W4; a.out = W5;
+  a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
+  a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s0); }));
+  ContigArgs z{};
+  z.in = W5; z.out = nullptr; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
+  z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = img_fk;
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->fk->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s0); }));
+  // join and mix (Eq. 10)
+  HIP_TRY(ctx, hipStreamWaitEvent(s0, ctx->fork[2], 0));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_MOE_MIX, [&] {
+    return nlos::launch_moe_mix(img_fk, img_rsd, d_img, (int)(nx * ny), p->beta, p->eps, mx, s0);
+  }));
   return NLOS_OK;
 }
 

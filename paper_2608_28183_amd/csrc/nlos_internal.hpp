@@ -61,6 +61,7 @@ struct FkXArgs {
   int nx, nt;
   float tscale;        // 1 / (nt - 1)
   const int* e_out;    // FP16 output: written as value * 2^(*e_out)
+  int unscaled;        // 1: plain x-FFT of tau (no t/(nt-1) factor, which then comes later)
 };
 
 // f-k pass 3: input half spectrum in[ky][kx <= Mx/2][nt] (row stride in_row), output full
@@ -74,6 +75,19 @@ struct FkPairArgs {
   float norm;          // 1 / (Mx My Mt)
   const int* e_in;     // FP16: input holds value * 2^(*e_in), output is written
   const int* e_out;    // as value * 2^(*e_out)
+  float tscale_in;     // non-zero: input sample t is first multiplied by t * tscale_in
+};
+
+// Mixture of experts, phasors from the shared spatial half spectrum: for each column
+// pair of in[ky][kx <= Mx/2][nt] (row stride in_row), the nt-point DFT of the column
+// gives out[ky * Mx + kx][f] = X[bins[f]] and, for the mirror column (-kx, -ky) of the
+// real input, out[.][f] = conj X[nt - bins[f]].
+struct MoePhasorArgs {
+  const float2* in;
+  float2* out;         // [My * Mx][nbins]
+  long long in_row, nwork;
+  int nt, Mx, My, nbins;
+  const int* bins;
 };
 
 // Radial propagation over chunks of pixels that share the lower radial bin.
@@ -98,6 +112,12 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
                          const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s, int sp = 0);
+hipError_t launch_moe_phasor_pair(const MoePhasorArgs& a, const float2* tw, hipStream_t s);
+// img = max-normalised fk_img * (max-normalised rsd_img + eps)^beta, max-normalised
+// (images of n pixels; mx: 3 words of device scratch)
+hipError_t launch_moe_mix(const float* fk_img, const float* rsd_img, float* img, int n, float beta,
+                          float eps, unsigned int* mx, hipStream_t s);
+
 // FP16 storage scales of the f-k intermediates from the bound B = sum |tau| t/(nt-1)
 // (nt a power of two): partials[kScaleBlocks] scratch, exps[4] = the exponents of
 // W1/W2, W3, W4, W5; l_norm = log2(Mx My Mt), l_my = log2 My, l_mx = log2 Mx.

@@ -97,6 +97,14 @@ _SIGNATURES = {
     "nlos_rsd_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(_VP)]),
     "nlos_rsd_plan_destroy": (_ST, [_VP]),
     "nlos_rsd": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_moe_check": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc), ctypes.c_double,
+                             ctypes.c_double]),
+    "nlos_moe_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_moe_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc),
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_VP)]),
+    "nlos_moe_plan_destroy": (_ST, [_VP]),
+    "nlos_moe": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
 }
 
 _lib = None
@@ -170,7 +178,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 15
+NLOS_PASS_COUNT = 17
 
 
 def nlos_pass_name(p: int) -> str:
@@ -320,3 +328,33 @@ def nlos_rsd(ctx: int, plan: int, tau, vol=None, img=None, ws=None) -> None:
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().nlos_rsd(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
            "nlos_rsd", ctx)
+
+
+def nlos_moe_check(fk: nlos_fk_desc, rsd: "RsdDesc", beta: float = 0.3, eps: float = 1e-6) -> int:
+    return lib().nlos_moe_check(ctypes.byref(fk), ctypes.byref(rsd.c), beta, eps)
+
+
+def nlos_moe_workspace_bytes(fk: nlos_fk_desc, rsd: "RsdDesc") -> int:
+    out = ctypes.c_size_t()
+    _check(lib().nlos_moe_workspace_bytes(ctypes.byref(fk), ctypes.byref(rsd.c), ctypes.byref(out)),
+           "nlos_moe_workspace_bytes")
+    return out.value
+
+
+def nlos_moe_plan_create(ctx: int, fk: nlos_fk_desc, rsd: "RsdDesc", beta: float = 0.3,
+                         eps: float = 1e-6, shared_spectrum: bool = True) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().nlos_moe_plan_create(ctx, ctypes.byref(fk), ctypes.byref(rsd.c), beta, eps,
+                                      int(bool(shared_spectrum)), ctypes.byref(out)),
+           "nlos_moe_plan_create", ctx)
+    return out.value
+
+
+def nlos_moe_plan_destroy(plan: int) -> None:
+    _check(lib().nlos_moe_plan_destroy(plan), "nlos_moe_plan_destroy")
+
+
+def nlos_moe(ctx: int, plan: int, tau, img, img_fk=None, img_rsd=None, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_moe(ctx, plan, _ptr(tau), _ptr(img), _ptr(img_fk), _ptr(img_rsd), _ptr(ws), ws_bytes),
+           "nlos_moe", ctx)

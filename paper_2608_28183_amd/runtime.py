@@ -92,6 +92,41 @@ class RsdPlan:
             pass
 
 
+class MoePlan:
+    """Mixture of experts (Section 4.4, Eq. 10) of f-k and radial RSD on one transient."""
+
+    def __init__(self, ctx: Context, ny: int, nx: int, nt: int, wall_w: float, wall_h: float,
+                 bin_ps: float, pad: int, freq_bins, weights, n_depth: int, depth0: float,
+                 depth_step: float, beta: float = 0.3, eps: float = 1e-6, sigma_s: int = 2,
+                 sigma_t: int = 0, delta: float = 0.0, kernel_prec: str = "fp32",
+                 shared_spectrum: bool = True):
+        self.ctx = ctx
+        self.shape = (ny, nx, nt)
+        self.fk_desc = nlos.fk_desc(nx, ny, nt, wall_w, wall_h, bin_ps, pad, "fp32")
+        self.rsd_desc = nlos.RsdDesc(nx, ny, nt, wall_w / nx, wall_h / ny, bin_ps, pad, freq_bins,
+                                     weights, n_depth, depth0, depth_step, sigma_s, sigma_t, delta,
+                                     "fp32", kernel_prec)
+        self.ws_bytes = nlos.nlos_moe_workspace_bytes(self.fk_desc, self.rsd_desc)
+        self.handle = nlos.nlos_moe_plan_create(ctx.handle, self.fk_desc, self.rsd_desc, beta, eps,
+                                                shared_spectrum)
+
+    def workspace(self) -> torch.Tensor:
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
+
+    def __call__(self, tau: torch.Tensor, img: torch.Tensor, img_fk=None, img_rsd=None, ws=None):
+        ny, nx, nt = self.shape
+        assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
+        assert img.shape == (ny, nx) and img.dtype == torch.float32
+        nlos.nlos_moe(self.ctx.handle, self.handle, tau, img, img_fk, img_rsd, ws)
+        return img, img_fk, img_rsd
+
+    def __del__(self):
+        try:
+            nlos.nlos_moe_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
 def bin_events(ctx: Context, events: torch.Tensor, n_events: int, hist: torch.Tensor, bin_ps: int,
                t0_ps: int = 0, accumulate: bool = False, dropped: "torch.Tensor | None" = None):
     """events: device tensor of n_events packed 8-byte records; hist: int32 [ny, nx, nt]."""

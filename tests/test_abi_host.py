@@ -163,3 +163,23 @@ def test_rsd_host_kernel_matches_oracle(name, nd):
     assert K.shape == ref.shape
     err = np.abs(K.astype(np.complex128) - ref).max() / np.abs(ref).max()
     assert err < 2e-7
+
+
+def test_moe_validation_and_workspace():
+    cfg = scenes.CONFIGS["c1"]
+    rd, _ = _rsd_desc(cfg)
+    fd = nlos.fk_desc(cfg.nx, cfg.ny, cfg.nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, pad=2)
+    assert nlos.nlos_moe_check(fd, rd) == nlos.NLOS_OK
+    # both branches must describe the same transient and grid
+    fd2 = nlos.fk_desc(cfg.nx, cfg.ny, cfg.nt, 2 * cfg.wall_w, cfg.wall_h, cfg.bin_ps, pad=2)
+    assert nlos.nlos_moe_check(fd2, rd) == nlos.NLOS_ERR_INVALID_ARG
+    fd3 = nlos.fk_desc(cfg.nx, cfg.ny, cfg.nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, pad=1)
+    assert nlos.nlos_moe_check(fd3, rd) == nlos.NLOS_ERR_INVALID_ARG
+    fd4 = nlos.fk_desc(cfg.nx, cfg.ny, cfg.nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, pad=2, prec="fp16")
+    assert nlos.nlos_moe_check(fd4, rd) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_moe_check(fd, rd, beta=-0.1) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.nlos_moe_check(fd, rd, eps=0.0) == nlos.NLOS_ERR_INVALID_ARG
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    want = up(nlos.nlos_fk_workspace_bytes(fd)) + up(nlos.nlos_rsd_workspace_bytes(rd)) + 256 + \
+        up(2 * 4 * cfg.nx * cfg.ny)
+    assert nlos.nlos_moe_workspace_bytes(fd, rd) == want
