@@ -201,8 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
-                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "moe_c4", "moe_c3",
-                             "copy_1GiB"],
+                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "phasor_c2", "moe_c4",
+                             "moe_c3", "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -304,6 +304,39 @@ def main():
 
         def sequential():
             sqp(tau, im2, None, None, ws)
+    elif kind == "phasor":
+        ev = scenes.config_events(cname, "shuffled")
+        d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)
+        p = scenes.rsd_params(cfg)
+        nf = len(p.freq_bins)
+        pplan = nlos.nlos_phasor_plan_create(ctx.handle, nlos.bin_desc(nx, ny, nt, int(cfg.bin_ps), 0, False),
+                                             p.freq_bins)
+        P = torch.empty((ny, nx, nf, 2), device=dev)
+        dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+        n = len(ev)
+        step = lambda: nlos.nlos_phasor_bin(ctx.handle, pplan, d_ev, n, P, dropped)  # noqa: E731
+        pass_bytes = {"phasor_bin": 8 * n + 8 * ny * nx * nf, "fill": 8 * ny * nx * nf}
+        metric, unit = "phasor_events_per_s", "events/s"
+        units_per_step = n
+        workload = {"workload": f"phasor binning of {n} events into {ny}x{nx} pixels x {nf} frequencies "
+                                f"(nt {nt})", "n_events": n, "shape": [ny, nx, nt], "n_freq": nf}
+        # photons -> RSD volume both ways: direct phasors, or histogram then the phasor DFT
+        rplan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
+                                p.weights, p.n_depth, p.depth0, p.depth_step)
+        rws = rplan.workspace()
+        rvol = torch.empty((ny, nx, p.n_depth), device=dev)
+        rimg = torch.empty((ny, nx), device=dev)
+        hist = torch.empty((ny, nx, nt), dtype=torch.int32, device=dev)
+        tau_h = torch.empty((ny, nx, nt), device=dev)
+
+        def via_phasors():
+            nlos.nlos_phasor_bin(ctx.handle, pplan, d_ev, n, P, dropped)
+            nlos.nlos_rsd_from_phasors(ctx.handle, rplan.handle, P, rvol, rimg, rws)
+
+        def via_histogram():
+            runtime.bin_events(ctx, d_ev, n, hist, int(cfg.bin_ps), 0, False, dropped)
+            nlos.nlos_counts_to_float(ctx.handle, hist, tau_h)
+            rplan(tau_h, rvol, rimg, rws)
     else:  # bin
         ev = scenes.config_events(cname, "shuffled")
         d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)
@@ -393,6 +426,20 @@ def main():
                    "moe_branches_in_sequence_ms": round(sq * 1e3, 4),
                    "separate_fk_then_rsd_ms": round(sep * 1e3, 4), "speedup_vs_separate": round(sep / sec, 3)}
 
+    phasor_cmp = None
+    if kind == "phasor":
+        def clock2(fn):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / args.steps
+        phasor_cmp = {"photons_to_rsd_via_phasor_binning_ms": round(clock2(via_phasors) * 1e3, 4),
+                      "photons_to_rsd_via_histogram_ms": round(clock2(via_histogram) * 1e3, 4)}
+
     line = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
@@ -402,6 +449,7 @@ def main():
         "passes_ms": {k: round(v, 4) for k, v in avg_ms.items()},
         "serving": serving,
         "moe_vs_separate": moe_cmp,
+        "phasor_vs_histogram": phasor_cmp,
         "step_frac_of_hbm": round(total_alg * value / units_per_step / (HBM_PEAK_GBS * 1e9), 4),
         "step_bytes": total_alg,
     }

@@ -51,6 +51,7 @@ typedef struct nlos_ctx nlos_ctx;
 typedef struct nlos_fk_plan nlos_fk_plan;
 typedef struct nlos_rsd_plan nlos_rsd_plan;
 typedef struct nlos_moe_plan nlos_moe_plan;
+typedef struct nlos_phasor_plan nlos_phasor_plan;
 
 /* ------------------------------------------------------------------------ */
 /* Context                                                                   */
@@ -93,7 +94,8 @@ typedef enum {
   NLOS_PASS_FK_SCALE = 14,     /* f-k FP16 storage scales from the input bound */
   NLOS_PASS_MOE_PHASOR = 15,   /* mixture of experts: RSD phasors from the shared spectrum */
   NLOS_PASS_MOE_MIX = 16,      /* mixture of experts: Eq. 10 on the branch images */
-  NLOS_PASS_COUNT = 17
+  NLOS_PASS_PHASOR_BIN = 17,   /* phasors straight from photon records */
+  NLOS_PASS_COUNT = 18
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
@@ -138,6 +140,23 @@ nlos_status nlos_bin(nlos_ctx *ctx, const nlos_bin_desc *desc, const nlos_event 
  * transient samples, d_tau[i] = (float)d_hist[i], so that a binned histogram can
  * feed nlos_fk / nlos_rsd.  Buffers may not overlap. */
 nlos_status nlos_counts_to_float(nlos_ctx *ctx, const uint32_t *d_hist, float *d_tau, uint64_t n);
+
+/* Phasors straight from photon records (Section 4.1, phasor binning, Listing 1): the
+ * plan holds the table exp(-2 pi i m / nt) (FP64-built, nt <= 2048, else
+ * NLOS_ERR_UNSUPPORTED) and the n_freq DFT bins freq_bin[f] in [0, nt) (host array,
+ * copied).  Validation of desc as for nlos_bin. */
+nlos_status nlos_phasor_plan_create(nlos_ctx *ctx, const nlos_bin_desc *desc, int n_freq, const int *freq_bin,
+                                    nlos_phasor_plan **out);
+nlos_status nlos_phasor_plan_destroy(nlos_phasor_plan *plan);
+/* Every valid event (as in nlos_bin) in bin b of its pixel adds
+ * exp(-2 pi i freq_bin[f] b / nt) to d_phasor[pixel][f] (float re, im pairs,
+ * [ny][nx][n_freq], 8-byte aligned; zeroed first unless desc->accumulate), which is the
+ * DFT at those bins of the histogram nlos_bin would build, up to rounding: hardware
+ * float atomics, one wave per event with its lanes over the frequencies, so the order of
+ * the sums (and the last bits) varies from run to run.  Dropped events are counted as
+ * in nlos_bin.  Feeds nlos_rsd_from_phasors. */
+nlos_status nlos_phasor_bin(nlos_ctx *ctx, const nlos_phasor_plan *plan, const nlos_event *d_events,
+                            uint64_t n_events, float *d_phasor, unsigned long long *d_dropped);
 
 /* ------------------------------------------------------------------------ */
 /* f-k migration (Section 4.2; Algorithms 1-2)                               */
@@ -244,6 +263,10 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan *plan);
  * NULL (not both).  Workspace as for nlos_fk. */
 nlos_status nlos_rsd(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
                      float *d_img, void *d_ws, size_t ws_bytes);
+/* nlos_rsd from phasors already at the plan's frequencies: d_phasor[ny][nx][n_freq]
+ * complex (float re, im; e.g. from nlos_phasor_bin with the same bins), read only. */
+nlos_status nlos_rsd_from_phasors(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_phasor, float *d_vol,
+                                  float *d_img, void *d_ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Mixture of experts of f-k and RSD (Section 4.4, Eq. 10)                   */

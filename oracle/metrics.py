@@ -4,10 +4,16 @@ from __future__ import annotations
 import numpy as np
 
 
+def _as_f64(a) -> np.ndarray:
+    a = np.asarray(a)
+    return a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+
+
 def rel_l2(x, ref) -> float:
-    """||x - ref|| / ||ref||; an all-zero reference is only matched by an all-zero x."""
-    x = np.asarray(x, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    """||x - ref|| / ||ref|| (complex values compared as complex); an all-zero reference is
+    only matched by an all-zero x."""
+    x = _as_f64(x)
+    ref = _as_f64(ref)
     n = np.linalg.norm(ref.ravel())
     d = np.linalg.norm((x - ref).ravel())
     if n == 0:

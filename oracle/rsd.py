@@ -44,6 +44,16 @@ def phasor(tau: np.ndarray, freq_bins) -> np.ndarray:
     return P.T.reshape(len(k), ny, nx)
 
 
+def phasor_from_events(pixel, t_ps, nx: int, ny: int, nt: int, bin_ps: int, t0_ps: int, freq_bins):
+    """Phasors straight from photon records (Section 4.1, phasor binning): each valid
+    event in bin b of its pixel adds exp(-2 pi i k_f b / nt) to P[f][pixel].  In exact
+    arithmetic this is the binner-side DFT of the histogram, which is how it is written
+    here (the histogram of the binning oracle, then `phasor`)."""
+    from .binning import bin_events
+    hist, dropped = bin_events(pixel, t_ps, nx, ny, nt, bin_ps, t0_ps)
+    return phasor(hist.astype(np.float64), freq_bins), dropped
+
+
 def wavenumbers(freq_bins, nt: int, c_dt: float) -> np.ndarray:
     """kappa_f = 2 pi k_f / (nt c dt) in rad/m (round-trip path units)."""
     return 2.0 * np.pi * np.asarray(freq_bins, dtype=np.float64) / (nt * c_dt)

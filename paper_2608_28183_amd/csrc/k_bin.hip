@@ -89,4 +89,69 @@ hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
   return hipGetLastError();
 }
 
+// Phasors straight from photon records (Section 4.1, phasor binning; the paper's warp
+// per photon becomes a wave64 per photon): a wave loads 64 events, then takes them one
+// at a time, its lanes striding over the frequencies; lane f adds the unit phasor
+// W_nt^(k_f b) of the event's bin b (from an LDS copy of the FP64-built table) to
+// P[pixel][f] with hardware float atomics.  Float sums in arbitrary order: equal to the
+// DFT of the histogram up to rounding.
+__global__ __launch_bounds__(256) void phasor_bin(const uint2* __restrict__ ev, unsigned long long n,
+                                                  float2* __restrict__ P, unsigned long long* __restrict__ dropped,
+                                                  int npix, int nt, uint32_t bin_ps, uint32_t t0,
+                                                  const float2* __restrict__ lut, const int* __restrict__ bins,
+                                                  int nf) {
+  __shared__ float2 slut[2048];
+  for (int i = threadIdx.x; i < nt; i += 256) slut[i] = lut[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const unsigned long long stride = (unsigned long long)gridDim.x * 256ull;
+  unsigned int drop = 0;
+  for (unsigned long long base = (unsigned long long)blockIdx.x * 256ull + (threadIdx.x & ~63u);
+       base < n; base += stride) {
+    const unsigned long long k = base + lane;
+    int pix = -1, b = 0;
+    if (k < n) {
+      const uint2 e = ev[k];
+      const int pixel = (int)e.x;
+      const uint32_t t = e.y;
+      if (pixel >= 0 && pixel < npix && t >= t0) {
+        const uint32_t bb = (t - t0) / bin_ps;
+        if (bb < (uint32_t)nt) {
+          pix = pixel;
+          b = (int)bb;
+        }
+      }
+      if (pix < 0) ++drop;
+    }
+    const unsigned long long valid = __ballot(pix >= 0);
+    for (unsigned long long m = valid; m != 0ull; m &= m - 1ull) {
+      const int j = __ffsll((long long)m) - 1;  // next valid event of the wave (uniform)
+      const int pj = __shfl(pix, j), bj = __shfl(b, j);
+      float2* row = P + (long long)pj * nf;
+      for (int f = lane; f < nf; f += 64) {
+        const float2 w = slut[(int)(((long long)bins[f] * bj) % nt)];
+        unsafeAtomicAdd(&row[f].x, w.x);
+        unsafeAtomicAdd(&row[f].y, w.y);
+      }
+    }
+  }
+  if (dropped != nullptr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+    if (lane == 0 && drop != 0) atomicAdd(dropped, (unsigned long long)drop);
+  }
+}
+
+hipError_t launch_phasor_bin(const void* events, unsigned long long n, float2* P, unsigned long long* dropped,
+                             int npix, int nt, uint32_t bin_ps, uint32_t t0, const float2* lut, const int* bins,
+                             int nf, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nt < 1 || nt > 2048 || nf < 1) return hipErrorInvalidValue;
+  unsigned long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(phasor_bin, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint2*>(events), n, P,
+                     dropped, npix, nt, bin_ps, t0, lut, bins, nf);
+  return hipGetLastError();
+}
+
 }  // namespace nlos

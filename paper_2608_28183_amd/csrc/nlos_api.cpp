@@ -174,7 +174,7 @@ static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
     "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale",
-    "moe_phasor", "moe_mix"};
+    "moe_phasor", "moe_mix", "phasor_bin"};
 
 extern "C" {
 
@@ -367,6 +367,86 @@ nlos_status nlos_counts_to_float(nlos_ctx* ctx, const uint32_t* d_hist, float* d
     return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_counts_to_float: buffers overlap");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] { return nlos::launch_u32_to_f32(d_hist, d_tau, n, ctx->stream); }));
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// phasor binning (Section 4.1)
+// ---------------------------------------------------------------------------
+
+struct nlos_phasor_plan {
+  nlos_bin_desc d{};
+  int device = 0;
+  int nf = 0;
+  float2* d_lut = nullptr;  // W_nt^m, m < nt (FP64-generated)
+  int* d_bins = nullptr;
+};
+
+nlos_status nlos_phasor_plan_destroy(nlos_phasor_plan* p) {
+  if (!p) return NLOS_OK;
+  (void)hipSetDevice(p->device);
+  if (p->d_lut) (void)hipFree(p->d_lut);
+  if (p->d_bins) (void)hipFree(p->d_bins);
+  delete p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_phasor_plan_create(nlos_ctx* ctx, const nlos_bin_desc* d, int n_freq, const int* freq_bin,
+                                    nlos_phasor_plan** out) {
+  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: NULL argument");
+  nlos_status st = nlos_bin_check(d);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  if (d->nt > 2048) return fail(ctx, NLOS_ERR_UNSUPPORTED, "phasor_plan_create: nt must be <= 2048");
+  if (n_freq < 1 || !freq_bin) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: need n_freq >= 1 and freq_bin");
+  for (int f = 0; f < n_freq; ++f)
+    if (freq_bin[f] < 0 || freq_bin[f] >= d->nt)
+      return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: freq_bin[%d] = %d outside [0, nt)", f, freq_bin[f]);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  nlos_phasor_plan* p = new (std::nothrow) nlos_phasor_plan();
+  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "phasor_plan_create: host allocation");
+  p->d = *d;
+  p->device = ctx->device;
+  p->nf = n_freq;
+  std::vector<float2> lut(d->nt);
+  for (int m = 0; m < d->nt; ++m) {
+    double c, sn;
+    nlos::cos_sin_2pi_frac(m, d->nt, &c, &sn);
+    lut[m] = make_float2((float)c, (float)-sn);  // exp(-2 pi i m / nt)
+  }
+  hipError_t e = hipMalloc(&p->d_lut, lut.size() * sizeof(float2));
+  if (e == hipSuccess) e = hipMalloc(&p->d_bins, n_freq * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(p->d_lut, lut.data(), lut.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_bins, freq_bin, n_freq * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    nlos_phasor_plan_destroy(p);
+    return fail(ctx, NLOS_ERR_DEVICE, "phasor_plan_create: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return NLOS_OK;
+}
+
+nlos_status nlos_phasor_bin(nlos_ctx* ctx, const nlos_phasor_plan* p, const nlos_event* d_events, uint64_t n_events,
+                            float* d_phasor, unsigned long long* d_dropped) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_phasor_bin: ctx or plan is NULL");
+  if (!d_phasor) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_phasor_bin: d_phasor is NULL");
+  if (n_events > 0 && !d_events) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_phasor_bin: d_events is NULL");
+  if (reinterpret_cast<uintptr_t>(d_events) % 8 != 0 || reinterpret_cast<uintptr_t>(d_phasor) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_phasor_bin: d_events and d_phasor must be 8-byte aligned");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_phasor_bin: plan of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const nlos_bin_desc& d = p->d;
+  const size_t nval = 2 * (size_t)d.nx * d.ny * p->nf;
+  if (!d.accumulate) {
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] { return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_phasor), nval, 0u, ctx->stream); }));
+    if (d_dropped)
+      HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+        return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_dropped), 2, 0u, ctx->stream);
+      }));
+  }
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_PHASOR_BIN, [&] {
+    return nlos::launch_phasor_bin(d_events, n_events, reinterpret_cast<float2*>(d_phasor), d_dropped, d.nx * d.ny,
+                                   d.nt, d.bin_ps, d.t0_ps, p->d_lut, p->d_bins, p->nf, ctx->stream);
+  }));
   return NLOS_OK;
 }
 
@@ -716,7 +796,7 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
 
 // The RSD pass sequence on stream s with workspace ws (validated by the caller).
 static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s, const float* d_tau, float* d_vol,
-                           float* d_img, void* ws) {
+                           float* d_img, void* ws, const float2* d_phasor = nullptr) {
   const nlos_rsd_desc& d = p->d;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const long long Nf = d.n_freq, Nd = d.n_depth;
@@ -733,14 +813,16 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
 
-  // 1. phasors: t-FFT of each pixel, bins k_f -> P[y][x][f]
-  ContigArgs c{};
-  c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
-  c.bins = p->d_bins; c.nbins = (int)Nf;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
+  // 1. phasors: t-FFT of each pixel, bins k_f -> P[y][x][f] (or the caller's phasors)
+  if (!d_phasor) {
+    ContigArgs c{};
+    c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
+    c.bins = p->d_bins; c.nbins = (int)Nf;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
+  }
   // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
-  a.in = P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
+  a.in = d_phasor ? d_phasor : P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
   a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
   // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
@@ -781,6 +863,22 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
   nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
   if (st != NLOS_OK) return st;
   return rsd_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ws);
+}
+
+nlos_status nlos_rsd_from_phasors(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_phasor, float* d_vol,
+                                  float* d_img, void* d_ws, size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: ctx or plan is NULL");
+  if (!d_phasor) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: d_phasor is NULL");
+  if (reinterpret_cast<uintptr_t>(d_phasor) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: d_phasor must be 8-byte aligned");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: plan of another device");
+  const RsdLayout L = rsd_layout(&p->d);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
+  if (st != NLOS_OK) return st;
+  return rsd_run(ctx, p, ctx->stream, nullptr, d_vol, d_img, ws, reinterpret_cast<const float2*>(d_phasor));
 }
 
 // ---------------------------------------------------------------------------

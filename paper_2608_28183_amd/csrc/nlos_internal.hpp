@@ -130,5 +130,9 @@ hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream
 hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
                       unsigned long long* dropped, int npix, int nt, uint32_t bin_ps, uint32_t t0,
                       hipStream_t s);
+// P[pixel][f] += W_nt^(bins[f] b) per valid event (nt <= 2048, lut = W_nt^m, m < nt)
+hipError_t launch_phasor_bin(const void* events, unsigned long long n, float2* P, unsigned long long* dropped,
+                             int npix, int nt, uint32_t bin_ps, uint32_t t0, const float2* lut, const int* bins,
+                             int nf, hipStream_t s);
 
 }  // namespace nlos

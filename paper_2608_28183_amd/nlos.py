@@ -97,6 +97,11 @@ _SIGNATURES = {
     "nlos_rsd_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(_VP)]),
     "nlos_rsd_plan_destroy": (_ST, [_VP]),
     "nlos_rsd": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_phasor_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_bin_desc), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_VP)]),
+    "nlos_phasor_plan_destroy": (_ST, [_VP]),
+    "nlos_phasor_bin": (_ST, [_VP, _VP, _VP, ctypes.c_uint64, _VP, _VP]),
+    "nlos_rsd_from_phasors": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
     "nlos_moe_check": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc), ctypes.c_double,
                              ctypes.c_double]),
     "nlos_moe_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc),
@@ -178,7 +183,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 17
+NLOS_PASS_COUNT = 18
 
 
 def nlos_pass_name(p: int) -> str:
@@ -358,3 +363,27 @@ def nlos_moe(ctx: int, plan: int, tau, img, img_fk=None, img_rsd=None, ws=None) 
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().nlos_moe(ctx, plan, _ptr(tau), _ptr(img), _ptr(img_fk), _ptr(img_rsd), _ptr(ws), ws_bytes),
            "nlos_moe", ctx)
+
+
+def nlos_phasor_plan_create(ctx: int, desc: nlos_bin_desc, freq_bins: Sequence[int]) -> int:
+    n = len(freq_bins)
+    arr = (ctypes.c_int32 * n)(*[int(k) for k in freq_bins])
+    out = ctypes.c_void_p()
+    _check(lib().nlos_phasor_plan_create(ctx, ctypes.byref(desc), n, arr, ctypes.byref(out)),
+           "nlos_phasor_plan_create", ctx)
+    return out.value
+
+
+def nlos_phasor_plan_destroy(plan: int) -> None:
+    _check(lib().nlos_phasor_plan_destroy(plan), "nlos_phasor_plan_destroy")
+
+
+def nlos_phasor_bin(ctx: int, plan: int, events, n_events: int, phasor, dropped=None) -> None:
+    _check(lib().nlos_phasor_bin(ctx, plan, _ptr(events), n_events, _ptr(phasor), _ptr(dropped)),
+           "nlos_phasor_bin", ctx)
+
+
+def nlos_rsd_from_phasors(ctx: int, plan: int, phasor, vol=None, img=None, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_rsd_from_phasors(ctx, plan, _ptr(phasor), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
+           "nlos_rsd_from_phasors", ctx)

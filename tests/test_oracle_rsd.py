@@ -142,3 +142,29 @@ def test_propagation_scalar_loop_8x8():
                     h = a * ((1 - al) * st.K[i0, f, d] + al * st.K[i1, f, d])
                     ref[d, u, v] += p.weights[f] * Ph[f, u, v] * h
     assert np.max(np.abs(C - ref)) < 1e-12 * np.abs(ref).max()
+
+
+def test_phasor_from_events_is_the_per_event_sum():
+    """Brute force on a tiny input: the sum over events of their unit phasors."""
+    import scenes
+    nx, ny, nt, bin_ps = 3, 2, 16, 10
+    ev = scenes.random_events(300, nx, ny, nt, bin_ps, seed=11, invalid_frac=0.1)
+    bins = [1, 3, 7]
+    P, dropped = orsd.phasor_from_events(ev["pixel"], ev["t_ps"], nx, ny, nt, bin_ps, 0, bins)
+    ref = np.zeros((len(bins), ny * nx), dtype=np.complex128)
+    nd = 0
+    for pix, t in zip(ev["pixel"].tolist(), ev["t_ps"].tolist()):
+        b = t // bin_ps
+        if not (0 <= pix < nx * ny) or b >= nt:
+            nd += 1
+            continue
+        for i, k in enumerate(bins):
+            ref[i, pix] += complex(math.cos(2 * math.pi * k * b / nt), -math.sin(2 * math.pi * k * b / nt))
+    assert nd == dropped
+    np.testing.assert_allclose(P.reshape(len(bins), -1), ref, rtol=0, atol=1e-9)
+
+
+def test_rel_l2_compares_complex_values_as_complex():
+    a = np.array([1 + 1j, 2 - 1j])
+    b = np.array([1 + 1j, 2 + 1j])
+    assert rel_l2(a, b) == pytest.approx(2 / np.sqrt(7), rel=1e-15)
