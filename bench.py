@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
                     choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "phasor_c2", "moe_c4",
-                             "moe_c3", "copy_1GiB"],
+                             "moe_c3", "merge_c4", "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -304,6 +304,31 @@ def main():
 
         def sequential():
             sqp(tau, im2, None, None, ws)
+    elif kind == "merge":
+        # one frame = the complex f-k field of a transient, then coherence merging over the
+        # last 3 frames (Eq. 8-9); the input alternates between two noise draws
+        taus = [torch.from_numpy(scenes.config_transient(cname)).to(dev),
+                torch.from_numpy(scenes.transient(cfg, seed=cfg.seed + 1)).to(dev)]
+        plan = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad)
+        ws = plan.workspace()
+        psi = torch.empty((ny, nx, nt, 2), device=dev)
+        merged = torch.empty((ny, nx, nt), device=dev)
+        coh = torch.empty((ny, nx, nt), device=dev)
+        window = 3
+        mstate = nlos.nlos_merge_create(ctx.handle, ny * nx * nt, window, 1e-6)
+        counter = [0]
+
+        def step():
+            nlos.nlos_fk_complex(ctx.handle, plan.handle, taus[counter[0] & 1], psi, ws)
+            nlos.nlos_merge_push(ctx.handle, mstate, psi, merged, coh)
+            counter[0] += 1
+        pass_bytes = fk_pass_bytes(ny, nx, nt, cfg.pad)
+        pass_bytes["fk_zi"] = 16 * ny * nx * nt
+        pass_bytes["merge"] = (8 + 8 + 8 * (window - 1) + 8) * ny * nx * nt
+        metric, unit = "merged_fk_volumes_per_s", "volumes/s"
+        units_per_step = 1
+        workload = {"workload": f"complex f-k field {ny}x{nx}x{nt} padded x{cfg.pad} + coherence merging "
+                                f"over {window} frames", "shape": [ny, nx, nt], "window": window}
     elif kind == "phasor":
         ev = scenes.config_events(cname, "shuffled")
         d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)

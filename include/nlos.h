@@ -52,6 +52,7 @@ typedef struct nlos_fk_plan nlos_fk_plan;
 typedef struct nlos_rsd_plan nlos_rsd_plan;
 typedef struct nlos_moe_plan nlos_moe_plan;
 typedef struct nlos_phasor_plan nlos_phasor_plan;
+typedef struct nlos_merge nlos_merge;
 
 /* ------------------------------------------------------------------------ */
 /* Context                                                                   */
@@ -95,7 +96,8 @@ typedef enum {
   NLOS_PASS_MOE_PHASOR = 15,   /* mixture of experts: RSD phasors from the shared spectrum */
   NLOS_PASS_MOE_MIX = 16,      /* mixture of experts: Eq. 10 on the branch images */
   NLOS_PASS_PHASOR_BIN = 17,   /* phasors straight from photon records */
-  NLOS_PASS_COUNT = 18
+  NLOS_PASS_MERGE = 18,        /* coherence-weighted temporal merging */
+  NLOS_PASS_COUNT = 19
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
@@ -301,6 +303,36 @@ nlos_status nlos_moe_plan_destroy(nlos_moe_plan *plan);
  * an all-zero image stays zero.  Workspace as for nlos_fk. */
 nlos_status nlos_moe(nlos_ctx *ctx, const nlos_moe_plan *plan, const float *d_tau, float *d_img,
                      float *d_img_fk, float *d_img_rsd, void *d_ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Complex fields and coherence-weighted temporal merging (Section 4.4,      */
+/* Eq. 8-9)                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* nlos_fk without the magnitude: d_psi[ny][nx][nt] = Psi (complex, float re, im pairs,
+ * 8-byte aligned), the field whose |.|^2 nlos_fk returns.  FP32 plans only
+ * (NLOS_ERR_UNSUPPORTED otherwise).  Workspace as for nlos_fk. */
+nlos_status nlos_fk_complex(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_psi,
+                            void *d_ws, size_t ws_bytes);
+/* nlos_rsd without the magnitude: d_field[ny][nx][n_depth] = I (complex), the field
+ * whose |.| nlos_rsd returns. */
+nlos_status nlos_rsd_complex(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_field,
+                             void *d_ws, size_t ws_bytes);
+
+/* Merging state over a window of up to `window` (1..64) complex frames of n_values
+ * each (device ring buffer of window * n_values * 8 bytes, owned by the state). */
+nlos_status nlos_merge_create(nlos_ctx *ctx, uint64_t n_values, int window, double eps, nlos_merge **out);
+nlos_status nlos_merge_destroy(nlos_merge *merge);
+/* Forgets the frames pushed so far (host only). */
+nlos_status nlos_merge_reset(nlos_merge *merge);
+/* Adds frame i (complex, n_values) and, over the W = min(i + 1, window) most recent
+ * frames f_j, writes
+ *   d_coherence = C = |sum f_j| / (eps + sum |f_j|)   (0 <= C < 1; nullable),
+ *   d_merged    = C |sum f_j| / W,
+ * the sums taken oldest first.  Calls on one state are ordered by the context's stream;
+ * a state must not be pushed from two streams at once. */
+nlos_status nlos_merge_push(nlos_ctx *ctx, nlos_merge *merge, const float *d_frame, float *d_merged,
+                            float *d_coherence);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,7 @@ Modules
               supplementary sampling rules, Algorithm 4) plus the exact dense
               and direct-sum RSD used as pins
   moe      -- mixture of experts of the two (Section 4.4, Eq. 10)
+  merge    -- coherence-weighted temporal merging (Section 4.4, Eq. 8-9)
   metrics  -- error measures (relative L2, PSNR, argmax distance)
 
 Every function states the passage it follows.  Readings of silent or garbled

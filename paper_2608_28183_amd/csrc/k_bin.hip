@@ -154,4 +154,43 @@ hipError_t launch_phasor_bin(const void* events, unsigned long long n, float2* P
   return hipGetLastError();
 }
 
+// Coherence-weighted merging (Section 4.4, Eq. 8-9) over the most recent `count` frames:
+// S = sum f_j, A = sum |f_j| (oldest first), C = |S| / (eps + A), merged = C |S| / count.
+// The new frame is stored into its ring slot in the same pass.
+__global__ __launch_bounds__(256) void merge_frames(const float2* __restrict__ frame, float2* __restrict__ ring,
+                                                    long long n, int window, int slot, int first, int count,
+                                                    float eps, float* __restrict__ merged,
+                                                    float* __restrict__ coherence) {
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < n; v += (long long)gridDim.x * 256) {
+    const float2 f = frame[v];
+    ring[(long long)slot * n + v] = f;
+    float2 S = make_float2(0.f, 0.f);
+    float A = 0.f;
+    for (int k = 0; k < count; ++k) {
+      int r = first + k;
+      if (r >= window) r -= window;
+      const float2 g = (r == slot) ? f : ring[(long long)r * n + v];
+      S.x += g.x;
+      S.y += g.y;
+      A += sqrtf(g.x * g.x + g.y * g.y);
+    }
+    const float s = sqrtf(S.x * S.x + S.y * S.y);
+    const float C = s / (eps + A);
+    merged[v] = C * s / (float)count;
+    if (coherence) coherence[v] = C;
+  }
+}
+
+hipError_t launch_merge(const float2* frame, float2* ring, long long n, int window, int slot, int first,
+                        int count, float eps, float* merged, float* coherence, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (window < 1 || slot < 0 || slot >= window || first < 0 || first >= window || count < 1 || count > window)
+    return hipErrorInvalidValue;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(merge_frames, dim3((unsigned)blocks), dim3(256), 0, s, frame, ring, n, window, slot, first,
+                     count, eps, merged, coherence);
+  return hipGetLastError();
+}
+
 }  // namespace nlos

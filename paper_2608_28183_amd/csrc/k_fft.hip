@@ -74,9 +74,10 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
     return;
   }
   auto store = [&](int n, float2 val) {
-    if constexpr (ST == ST_C64) {
+    if constexpr (ST == ST_C64 || ST == ST_C64_SCALED) {
       if (colok && n < a.n_out)
-        static_cast<float2*>(a.out)[plane * a.out_plane + (long long)n * a.out_line + col] = val;
+        static_cast<float2*>(a.out)[plane * a.out_plane + (long long)n * a.out_line + col] =
+            ST == ST_C64_SCALED ? cscale(val, a.oscale) : val;
     } else {  // |v|^2 or |v| (times a.oscale) plus a max over this tile's columns into img
       float m = val.x * val.x + val.y * val.y;
       if constexpr (ST == ST_ABS_IMG) m = sqrtf(m);
@@ -262,6 +263,8 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
     return launch_strided_inv<true, LD_C64, ST_ABS2_IMG>(n, a, nplanes, tw, s);
   if (inverse && ld == LD_C64 && st == ST_ABS_IMG)
     return launch_strided_inv<true, LD_C64, ST_ABS_IMG>(n, a, nplanes, tw, s);
+  if (inverse && ld == LD_C64 && st == ST_C64_SCALED)
+    return launch_strided_inv<true, LD_C64, ST_C64_SCALED>(n, a, nplanes, tw, s);
   return hipErrorInvalidValue;
 }
 
@@ -304,6 +307,8 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
     return launch_contig_inv<true, CL_C64, CS_ABS_IMG>(n, a, tw, s);
   if (inverse && ld == CL_C64 && st == CS_ABS2_MAX)
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX>(n, a, tw, s);
+  if (inverse && ld == CL_C64 && st == CS_C64)
+    return launch_contig_inv<true, CL_C64, CS_C64>(n, a, tw, s);
   return hipErrorInvalidValue;
 }
 

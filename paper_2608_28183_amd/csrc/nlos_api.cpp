@@ -174,7 +174,7 @@ static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
     "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale",
-    "moe_phasor", "moe_mix", "phasor_bin"};
+    "moe_phasor", "moe_mix", "phasor_bin", "merge"};
 
 extern "C" {
 
@@ -510,7 +510,7 @@ nlos_status nlos_fk_plan_destroy(nlos_fk_plan* p) {
 
 // The f-k pass sequence on stream s with workspace ws (validated by the caller).
 static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, const float* d_tau, float* d_vol,
-                          float* d_img, void* ws) {
+                          float* d_img, void* ws, float2* d_psi = nullptr) {
   const nlos_fk_desc& d = p->d;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const FkLayout L = fk_layout(&d);
@@ -584,6 +584,11 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   z.in = W5; z.out = d_vol; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
   z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = d_img;
   z.e_in = ex ? ex + 3 : nullptr;
+  if (d_psi) {  // the complex field Psi itself (FP32 path)
+    z.out = d_psi; z.img = nullptr;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_C64, z, tw, s); }));
+    return NLOS_OK;
+  }
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp); }));
   return NLOS_OK;
 }
@@ -796,7 +801,7 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
 
 // The RSD pass sequence on stream s with workspace ws (validated by the caller).
 static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s, const float* d_tau, float* d_vol,
-                           float* d_img, void* ws, const float2* d_phasor = nullptr) {
+                           float* d_img, void* ws, const float2* d_phasor = nullptr, float2* d_field = nullptr) {
   const nlos_rsd_desc& d = p->d;
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const long long Nf = d.n_freq, Nd = d.n_depth;
@@ -847,6 +852,11 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   a.in = D; a.out = d_vol; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
   a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
+  if (d_field) {  // the complex field I itself
+    a.out = d_field; a.img = nullptr;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64_SCALED, a, (int)ny, tw, s); }));
+    return NLOS_OK;
+  }
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s); }));
   return NLOS_OK;
 }
@@ -879,6 +889,102 @@ nlos_status nlos_rsd_from_phasors(nlos_ctx* ctx, const nlos_rsd_plan* p, const f
   nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
   if (st != NLOS_OK) return st;
   return rsd_run(ctx, p, ctx->stream, nullptr, d_vol, d_img, ws, reinterpret_cast<const float2*>(d_phasor));
+}
+
+nlos_status nlos_fk_complex(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_psi, void* d_ws,
+                            size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_complex: ctx or plan is NULL");
+  if (!d_tau || !d_psi) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_complex: d_tau and d_psi are required");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0 || reinterpret_cast<uintptr_t>(d_psi) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_complex: d_tau and d_psi must be 8-byte aligned");
+  if (p->d.prec != NLOS_FP32) return fail(ctx, NLOS_ERR_UNSUPPORTED, "nlos_fk_complex: FP32 plans only");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_complex: plan of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, fk_layout(&p->d).bytes, &ws);
+  if (st != NLOS_OK) return st;
+  return fk_run(ctx, p, ctx->stream, d_tau, nullptr, nullptr, ws, reinterpret_cast<float2*>(d_psi));
+}
+
+nlos_status nlos_rsd_complex(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, float* d_field, void* d_ws,
+                             size_t ws_bytes) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: ctx or plan is NULL");
+  if (!d_tau || !d_field) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: d_tau and d_field are required");
+  if (reinterpret_cast<uintptr_t>(d_field) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: d_field must be 8-byte aligned");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: plan of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).total * 8, &ws);
+  if (st != NLOS_OK) return st;
+  return rsd_run(ctx, p, ctx->stream, d_tau, nullptr, nullptr, ws, nullptr, reinterpret_cast<float2*>(d_field));
+}
+
+// ---------------------------------------------------------------------------
+// coherence-weighted temporal merging (Section 4.4, Eq. 8-9)
+// ---------------------------------------------------------------------------
+
+struct nlos_merge {
+  int device = 0;
+  long long n = 0;
+  int window = 0;
+  float eps = 0.f;
+  long long pushed = 0;      // frames since the last reset
+  float2* ring = nullptr;    // [window][n]
+};
+
+nlos_status nlos_merge_create(nlos_ctx* ctx, uint64_t n_values, int window, double eps, nlos_merge** out) {
+  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_create: NULL argument");
+  if (n_values == 0 || window < 1 || window > 64 || !(eps > 0.0) || !std::isfinite(eps))
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_create: need n_values >= 1, window in [1, 64], eps > 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  nlos_merge* m = new (std::nothrow) nlos_merge();
+  if (!m) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "merge_create: host allocation");
+  m->device = ctx->device;
+  m->n = (long long)n_values;
+  m->window = window;
+  m->eps = (float)eps;
+  hipError_t e = hipMalloc(&m->ring, (size_t)window * n_values * sizeof(float2));
+  if (e != hipSuccess) {
+    delete m;
+    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE, "merge_create: %s",
+                hipGetErrorString(e));
+  }
+  *out = m;
+  return NLOS_OK;
+}
+
+nlos_status nlos_merge_destroy(nlos_merge* m) {
+  if (!m) return NLOS_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  if (m->ring) (void)hipFree(m->ring);
+  delete m;
+  return NLOS_OK;
+}
+
+nlos_status nlos_merge_reset(nlos_merge* m) {
+  if (!m) return fail(nullptr, NLOS_ERR_INVALID_ARG, "merge_reset: NULL");
+  m->pushed = 0;
+  return NLOS_OK;
+}
+
+nlos_status nlos_merge_push(nlos_ctx* ctx, nlos_merge* m, const float* d_frame, float* d_merged, float* d_coherence) {
+  if (!ctx || !m) return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_push: ctx or merge is NULL");
+  if (!d_frame || !d_merged) return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_push: d_frame and d_merged are required");
+  if (reinterpret_cast<uintptr_t>(d_frame) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_push: d_frame must be 8-byte aligned");
+  if (m->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "merge_push: state of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int slot = (int)(m->pushed % m->window);
+  const int count = (int)std::min<long long>(m->pushed + 1, m->window);
+  const int first = (int)((m->pushed + 1 - count) % m->window);
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_MERGE, [&] {
+    return nlos::launch_merge(reinterpret_cast<const float2*>(d_frame), m->ring, m->n, m->window, slot, first, count,
+                              m->eps, d_merged, d_coherence, ctx->stream);
+  }));
+  ++m->pushed;
+  return NLOS_OK;
 }
 
 // ---------------------------------------------------------------------------

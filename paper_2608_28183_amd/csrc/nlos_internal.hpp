@@ -13,7 +13,7 @@ enum { SP_F32 = 0, SP_F16 = 1, SP_BF16 = 2 };
 
 // strided_fft load / store modes
 enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
-enum { ST_C64 = 0, ST_ABS2_IMG = 1, ST_ABS_IMG = 2 };
+enum { ST_C64 = 0, ST_ABS2_IMG = 1, ST_ABS_IMG = 2, ST_C64_SCALED = 3 };
 // contig_fft load / store modes
 enum { CL_C64 = 0, CL_REAL = 1 };
 enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2, CS_ABS2_MAX = 3 };
@@ -28,7 +28,7 @@ struct StridedArgs {
   long long out_plane, out_line;
   int ncols, n_in, n_out;
   float tscale;        // LD_TAU_SCALED: the sample in column t is scaled by t * tscale
-  float oscale;        // ST_ABS2_IMG: output = |v|^2 * oscale; ST_ABS_IMG: |v| * oscale
+  float oscale;        // ST_ABS2_IMG: |v|^2 * oscale; ST_ABS_IMG: |v| * oscale; ST_C64_SCALED: v * oscale
   float* img;          // ST_ABS*_IMG: img[plane * img_plane + n] = max over columns (may be null)
   long long img_plane;
   // four-byte storage (SP_F16 / SP_BF16): an FP16 input holds value * 2^(*e_in) and an
@@ -113,6 +113,11 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
 hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_moe_phasor_pair(const MoePhasorArgs& a, const float2* tw, hipStream_t s);
+// coherence-weighted merging over a ring of `window` complex frames of n values:
+// writes `frame` into ring slot `slot`, then sums the `count` most recent frames (ring
+// slots first, first + 1, ... mod window, oldest first)
+hipError_t launch_merge(const float2* frame, float2* ring, long long n, int window, int slot, int first,
+                        int count, float eps, float* merged, float* coherence, hipStream_t s);
 // img = max-normalised fk_img * (max-normalised rsd_img + eps)^beta, max-normalised
 // (images of n pixels; mx: 3 words of device scratch)
 hipError_t launch_moe_mix(const float* fk_img, const float* rsd_img, float* img, int n, float beta,

@@ -102,6 +102,12 @@ _SIGNATURES = {
     "nlos_phasor_plan_destroy": (_ST, [_VP]),
     "nlos_phasor_bin": (_ST, [_VP, _VP, _VP, ctypes.c_uint64, _VP, _VP]),
     "nlos_rsd_from_phasors": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_fk_complex": (_ST, [_VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_rsd_complex": (_ST, [_VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_merge_create": (_ST, [_VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_VP)]),
+    "nlos_merge_destroy": (_ST, [_VP]),
+    "nlos_merge_reset": (_ST, [_VP]),
+    "nlos_merge_push": (_ST, [_VP, _VP, _VP, _VP, _VP]),
     "nlos_moe_check": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc), ctypes.c_double,
                              ctypes.c_double]),
     "nlos_moe_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc),
@@ -183,7 +189,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 18
+NLOS_PASS_COUNT = 19
 
 
 def nlos_pass_name(p: int) -> str:
@@ -387,3 +393,31 @@ def nlos_rsd_from_phasors(ctx: int, plan: int, phasor, vol=None, img=None, ws=No
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().nlos_rsd_from_phasors(ctx, plan, _ptr(phasor), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
            "nlos_rsd_from_phasors", ctx)
+
+
+def nlos_fk_complex(ctx: int, plan: int, tau, psi, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_fk_complex(ctx, plan, _ptr(tau), _ptr(psi), _ptr(ws), ws_bytes), "nlos_fk_complex", ctx)
+
+
+def nlos_rsd_complex(ctx: int, plan: int, tau, field, ws=None) -> None:
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nlos_rsd_complex(ctx, plan, _ptr(tau), _ptr(field), _ptr(ws), ws_bytes), "nlos_rsd_complex", ctx)
+
+
+def nlos_merge_create(ctx: int, n_values: int, window: int, eps: float = 1e-6) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().nlos_merge_create(ctx, n_values, window, eps, ctypes.byref(out)), "nlos_merge_create", ctx)
+    return out.value
+
+
+def nlos_merge_destroy(merge: int) -> None:
+    _check(lib().nlos_merge_destroy(merge), "nlos_merge_destroy")
+
+
+def nlos_merge_reset(merge: int) -> None:
+    _check(lib().nlos_merge_reset(merge), "nlos_merge_reset")
+
+
+def nlos_merge_push(ctx: int, merge: int, frame, merged, coherence=None) -> None:
+    _check(lib().nlos_merge_push(ctx, merge, _ptr(frame), _ptr(merged), _ptr(coherence)), "nlos_merge_push", ctx)
