@@ -115,7 +115,7 @@ __device__ __forceinline__ PairItem pair_item(long long w, int Mx, int My) {
   return it;
 }
 
-template <int N, int E_ = default_e(N), int SP = SP_F32>
+template <int N, int E_ = default_e(N), int SP = SP_F32, bool TSCALE = false>
 __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(FkPairArgs a,
                                                                              const float2* __restrict__ tw) {
   using C = ContigCfg<N, E_>;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
         v[j] = ST_::cvt(raw[j]);
         if constexpr (SP == SP_F16) v[j] = ldexp2(v[j], e);
       }
-      if (a.tscale_in != 0.f) {
+      if constexpr (TSCALE) {  // separate instantiation: keeps the plain pass's registers
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = cscale(v[j], float(p + j * P) * a.tscale_in);
       }
@@ -464,7 +464,12 @@ static hipError_t launch_pair_n(const FkPairArgs& a, const float2* tw, hipStream
   using C = ContigCfg<N, E>;
   const long long groups = (a.nwork + C::L - 1) / C::L;
   dim3 grid((unsigned)(groups < kColumnBlocks ? groups : kColumnBlocks));
-  hipLaunchKernelGGL((fk_column_pair<N, E, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
+  if (SP == SP_F32 && a.tscale_in != 0.f)
+    hipLaunchKernelGGL((fk_column_pair<N, E, SP_F32, true>), grid, dim3(C::THREADS), 0, s, a, tw);
+  else if (a.tscale_in == 0.f)
+    hipLaunchKernelGGL((fk_column_pair<N, E, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
+  else
+    return hipErrorInvalidValue;  // input scaling is built for FP32 storage only
   return hipGetLastError();
 }
 
