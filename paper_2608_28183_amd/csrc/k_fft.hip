@@ -107,7 +107,10 @@ struct ContigTune {
   static constexpr int E = default_e(N);
 };
 
-template <int N, bool INV, int LD, int ST, int SP = SP_F32>
+// HALF: the line's upper half is zero padding (n_in = N/2) and only the lower half of the
+// outputs is kept (n_out = N/2), both known at compile time, so the zero inputs fold out
+// of the first radix stage and the unused outputs out of the last.
+template <int N, bool INV, int LD, int ST, int SP = SP_F32, bool HALF = false>
 __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void contig_fft(
     ContigArgs a, const float2* __restrict__ tw) {
   using C = ContigCfg<N, ContigTune<N>::E>;
@@ -127,7 +130,8 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
         constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
         const int n = stage_in_index<N, S::R0, E>(p, b, r);
         float2 x = make_float2(0.f, 0.f);
-        if (lineok && n < a.n_in) {
+        constexpr bool ZERO = HALF && (b * (N / E) + r * (N / S::R0) >= N / 2);  // n >= N/2 for every p
+        if (!ZERO && lineok && n < (HALF ? N / 2 : a.n_in)) {
           const long long i = line * a.in_line + n;
           if constexpr (LD == CL_REAL) {
             x.x = static_cast<const float*>(a.in)[i];
@@ -143,7 +147,17 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
     using ST_ = Stor<SP>;
     typename ST_::R raw[E];
     const typename ST_::T* in = static_cast<const typename ST_::T*>(a.in) + (lineok ? line : 0) * a.in_line;
-    load_first_stage<S>(raw, p, a.n_in, lineok, ST_::zero(), [&](int n) { return ST_::raw(in, n); });
+    if constexpr (HALF) {
+      static_assert(S::R0 == E, "first-stage radix equals the samples per thread");
+      static_for<E / 2>([&](auto r_) {
+        constexpr int r = decltype(r_)::value;
+        raw[r] = ST_::raw(in, p + r * P);
+        if (!lineok) raw[r] = ST_::zero();
+      });
+      static_for<E / 2>([&](auto r_) { raw[E / 2 + decltype(r_)::value] = ST_::zero(); });
+    } else {
+      load_first_stage<S>(raw, p, a.n_in, lineok, ST_::zero(), [&](int n) { return ST_::raw(in, n); });
+    }
     const int e = SP == SP_F16 ? -*a.e_in : 0;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -171,7 +185,7 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
     // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]
     float m = 0.f;
     auto store = [&](int n, float2 val) {
-      if (!lineok || n >= a.n_out) return;
+      if (!lineok || n >= (HALF ? N / 2 : a.n_out)) return;
       const float e = (val.x * val.x + val.y * val.y) * a.oscale;
       if (a.out != nullptr) static_cast<float*>(a.out)[line * a.out_line + n] = e;
       m = fmaxf(m, e);
@@ -268,32 +282,39 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
   return hipErrorInvalidValue;
 }
 
-template <int N, bool INV, int LD, int ST, int SP = SP_F32>
+template <int N, bool INV, int LD, int ST, int SP = SP_F32, bool HALF = false>
 static hipError_t launch_contig_n(const ContigArgs& a, const float2* tw, hipStream_t s) {
   using C = ContigCfg<N, ContigTune<N>::E>;
   dim3 grid((unsigned)((a.nlines + C::L - 1) / C::L));
-  hipLaunchKernelGGL((contig_fft<N, INV, LD, ST, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((contig_fft<N, INV, LD, ST, SP, HALF>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-template <bool INV, int LD, int ST, int SP = SP_F32>
+template <bool INV, int LD, int ST, int SP = SP_F32, bool HALF = false>
 static hipError_t launch_contig_inv(int n, const ContigArgs& a, const float2* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_contig_n<8, INV, LD, ST, SP>(a, tw, s);
-    case 16: return launch_contig_n<16, INV, LD, ST, SP>(a, tw, s);
-    case 32: return launch_contig_n<32, INV, LD, ST, SP>(a, tw, s);
-    case 64: return launch_contig_n<64, INV, LD, ST, SP>(a, tw, s);
-    case 128: return launch_contig_n<128, INV, LD, ST, SP>(a, tw, s);
-    case 256: return launch_contig_n<256, INV, LD, ST, SP>(a, tw, s);
-    case 512: return launch_contig_n<512, INV, LD, ST, SP>(a, tw, s);
-    case 1024: return launch_contig_n<1024, INV, LD, ST, SP>(a, tw, s);
-    case 2048: return launch_contig_n<2048, INV, LD, ST, SP>(a, tw, s);
+    case 8: return launch_contig_n<8, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 16: return launch_contig_n<16, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 32: return launch_contig_n<32, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 64: return launch_contig_n<64, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 128: return launch_contig_n<128, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 256: return launch_contig_n<256, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 512: return launch_contig_n<512, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 1024: return launch_contig_n<1024, INV, LD, ST, SP, HALF>(a, tw, s);
+    case 2048: return launch_contig_n<2048, INV, LD, ST, SP, HALF>(a, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a, const float2* tw,
                          hipStream_t s, int sp) {
+  // the f-k z pass of a padded volume: half the line in, half out
+  const bool half = inverse && ld == CL_C64 && st == CS_ABS2_MAX && 2 * a.n_in == n && 2 * a.n_out == n;
+  if (half) {
+    if (sp == SP_F16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16, true>(n, a, tw, s);
+    if (sp == SP_BF16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16, true>(n, a, tw, s);
+    if (sp == SP_F32) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F32, true>(n, a, tw, s);
+  }
   if (sp == SP_F16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16>(n, a, tw, s);
   if (sp == SP_BF16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
