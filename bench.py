@@ -419,12 +419,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and kind == "fk":
         try:
-            frac = 2
+            frac = 1
             est, spent = cpu_baseline_fk(cfg, frac)
             cpu = {"value": round(1.0 / est, 6), "unit": unit, "cores": blas_threads() or
                    len(os.sched_getaffinity(0)), "kind": "oracle",
-                   "sample": f"every FP64 oracle step on 1/{frac} of its independent slices of the "
-                             f"{cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt} volume, scaled x{frac} "
+                   "sample": f"every FP64 oracle step once on the full {cfg.pad*ny}x{cfg.pad*nx}x{cfg.pad*nt} "
+                             f"padded volume (random data of the same shape) "
                              f"({spent:.1f} s of CPU time measured)",
                    "host_cpus": len(os.sched_getaffinity(0))}
         except MemoryError:
