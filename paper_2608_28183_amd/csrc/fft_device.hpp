@@ -89,6 +89,22 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Non-temporal (streaming) global accesses for volumes that are read or written once per
+// pass and are far larger than the caches: they keep such lines from displacing the
+// ones the next pass can still reuse.
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+typedef float nlos_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_stream(float4* p, float4 v) {
+  const nlos_f4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<nlos_f4*>(p));
+}
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
 __device__ __forceinline__ float2 rot90(float2 a) {

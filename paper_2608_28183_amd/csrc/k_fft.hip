@@ -12,7 +12,8 @@
 
 namespace nlos {
 
-template <int N, int E, int T_, bool INV, int LD, int ST, int SP = SP_F32>
+// NT: non-temporal loads and stores of the FP32 complex lines (the f-k volumes)
+template <int N, int E, int T_, bool INV, int LD, int ST, int SP = SP_F32, bool NT = false>
 __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(StridedArgs a,
                                                                               const float2* __restrict__ tw) {
   using C = StridedCfg<N, E, T_>;
@@ -39,6 +40,8 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
           const long long i = plane * a.in_plane + (long long)n * a.in_line + col;
           if constexpr (LD == LD_TAU_SCALED) {
             x.x = static_cast<const float*>(a.in)[i] * (float(col) * a.tscale);
+          } else if constexpr (NT) {
+            x = ld_stream(static_cast<const float2*>(a.in) + i);
           } else {
             x = static_cast<const float2*>(a.in)[i];
           }
@@ -76,8 +79,15 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
   auto store = [&](int n, float2 val) {
     if constexpr (ST == ST_C64 || ST == ST_C64_SCALED) {
       if (colok && n < a.n_out)
-        static_cast<float2*>(a.out)[plane * a.out_plane + (long long)n * a.out_line + col] =
-            ST == ST_C64_SCALED ? cscale(val, a.oscale) : val;
+      {
+        const float2 w = ST == ST_C64_SCALED ? cscale(val, a.oscale) : val;
+        float2* dst = static_cast<float2*>(a.out) + plane * a.out_plane + (long long)n * a.out_line + col;
+        if constexpr (NT) {
+          st_stream(dst, w);
+        } else {
+          *dst = w;
+        }
+      }
     } else {  // |v|^2 or |v| (times a.oscale) plus a max over this tile's columns into img
       float m = val.x * val.x + val.y * val.y;
       if constexpr (ST == ST_ABS_IMG) m = sqrtf(m);
@@ -231,35 +241,38 @@ struct StridedTune {
   static constexpr int T = (N == 512) ? (WIDE ? 32 : 16) : (N == 256 ? (WIDE ? 64 : 32) : default_t(N));
 };
 
-template <int N, bool INV, int LD, int ST, int SP = SP_F32, int E = StridedTune<N, INV, LD, ST, SP>::E,
-          int T = StridedTune<N, INV, LD, ST, SP>::T>
+template <int N, bool INV, int LD, int ST, int SP = SP_F32, bool NT = false,
+          int E = StridedTune<N, INV, LD, ST, SP>::E, int T = StridedTune<N, INV, LD, ST, SP>::T>
 static hipError_t launch_strided_n(const StridedArgs& a, int nplanes, const float2* tw,
                                    hipStream_t s) {
   using C = StridedCfg<N, E, T>;
   dim3 grid((a.ncols + C::T - 1) / C::T, nplanes);
-  hipLaunchKernelGGL((strided_fft<N, E, T, INV, LD, ST, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
+  hipLaunchKernelGGL((strided_fft<N, E, T, INV, LD, ST, SP, NT>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();
 }
 
-template <bool INV, int LD, int ST, int SP = SP_F32>
+template <bool INV, int LD, int ST, int SP = SP_F32, bool NT = false>
 static hipError_t launch_strided_inv(int n, const StridedArgs& a, int nplanes, const float2* tw,
                                      hipStream_t s) {
   switch (n) {
-    case 8: return launch_strided_n<8, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 16: return launch_strided_n<16, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 32: return launch_strided_n<32, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 64: return launch_strided_n<64, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 128: return launch_strided_n<128, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 256: return launch_strided_n<256, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 512: return launch_strided_n<512, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 1024: return launch_strided_n<1024, INV, LD, ST, SP>(a, nplanes, tw, s);
-    case 2048: return launch_strided_n<2048, INV, LD, ST, SP>(a, nplanes, tw, s);
+    case 8: return launch_strided_n<8, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 16: return launch_strided_n<16, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 32: return launch_strided_n<32, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 64: return launch_strided_n<64, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 128: return launch_strided_n<128, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 256: return launch_strided_n<256, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 512: return launch_strided_n<512, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 1024: return launch_strided_n<1024, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
+    case 2048: return launch_strided_n<2048, INV, LD, ST, SP, NT>(a, nplanes, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
-                          const float2* tw, hipStream_t s, int sp) {
+                          const float2* tw, hipStream_t s, int sp, bool stream) {
+  if (stream && sp == SP_F32 && ld == LD_C64 && st == ST_C64)
+    return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_F32, true>(n, a, nplanes, tw, s)
+                   : launch_strided_inv<false, LD_C64, ST_C64, SP_F32, true>(n, a, nplanes, tw, s);
   if (sp == SP_F16 && ld == LD_C64 && st == ST_C64)
     return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_F16>(n, a, nplanes, tw, s)
                    : launch_strided_inv<false, LD_C64, ST_C64, SP_F16>(n, a, nplanes, tw, s);

@@ -77,7 +77,7 @@ __global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c(FkXArg
     // A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / (2i)
     const float4 ab = make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y),
                                   0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-    out[(long long)k * (a.nt / 2)] = ab;
+    st_stream(out + (long long)k * (a.nt / 2), ab);
   }
 }
 
@@ -154,7 +154,7 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
         static_for<E>([&](auto r_) {
           constexpr int r = decltype(r_)::value;
           const int n = p + r * P;
-          raw[r] = (ok && n < a.nt) ? in[n] : ST_::zero();
+          raw[r] = (ok && n < a.nt) ? ld_stream(in + n) : ST_::zero();
         });
       } else {
         load_first_stage<S>(raw, p, a.nt, ok, ST_::zero(), [&](int n) { return ST_::raw(in, n); });

@@ -554,7 +554,7 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
   a.e_in = ex; a.e_out = ex;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp, true); }));
   // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
   // column and its mirror; the remapped spectra (kz < nt) go to W3
   FkPairArgs c{};
@@ -570,14 +570,14 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true); }));
   // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
   a = StridedArgs{};
   a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true); }));
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
@@ -1136,7 +1136,7 @@ nlos_status nlos_moe(nlos_ctx* ctx, const nlos_moe_plan* p, const float* d_tau, 
   a.in = W1; a.out = W2;
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s0); }));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s0, nlos::SP_F32, true); }));
   // fork: the RSD branch on the second stream
   HIP_TRY(ctx, hipEventRecord(ctx->fork[0], s0));
   HIP_TRY(ctx, hipStreamWaitEvent(s1, ctx->fork[0], 0));
@@ -1174,12 +1174,12 @@ nlos_status nlos_moe(nlos_ctx* ctx, const nlos_moe_plan* p, const float* d_tau, 
   a.in = W3; a.out = W4;
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s0); }));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s0, nlos::SP_F32, true); }));
   a = StridedArgs{};
   a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s0); }));
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s0, nlos::SP_F32, true); }));
   ContigArgs z{};
   z.in = W5; z.out = nullptr; z.nlines = ny * nx; z.in_line = nt; z.out_line = nt;
   z.n_in = (int)nt; z.n_out = (int)nt; z.oscale = 1.0f; z.img = img_fk;

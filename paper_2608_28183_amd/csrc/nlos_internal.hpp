@@ -106,8 +106,9 @@ struct RsdPropArgs {
   int kernel_fp16;
 };
 
+// stream: non-temporal loads and stores (FP32 LD_C64 -> ST_C64 only; ignored otherwise)
 hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
-                          const float2* tw, hipStream_t s, int sp = 0);
+                          const float2* tw, hipStream_t s, int sp = 0, bool stream = false);
 hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& a,
                          const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp = 0);
