@@ -8,7 +8,7 @@ complete nlos_fk call (5 kernel passes + the image clear).  Prints one JSON
 line with volumes/s, the HBM roofline of the dominant kernel and the FP64
 oracle's CPU throughput on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload fk_c4|fk_c3|rsd_c3|rsd_c2|bin_c2]
+    python bench.py [--steps K] [--warmup W] [--workload fk_c4|fk_c3|fk_office|rsd_c3|rsd_c2|bin_c2]
 """
 from __future__ import annotations
 
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
-                    choices=["fk_c4", "fk_c3", "fk_c1", "rsd_c3", "rsd_c2", "bin_c2", "phasor_c2", "moe_c4",
+                    choices=["fk_c4", "fk_c3", "fk_c1", "fk_office", "rsd_c3", "rsd_c2", "bin_c2", "phasor_c2", "moe_c4",
                              "moe_c3", "merge_c4", "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")

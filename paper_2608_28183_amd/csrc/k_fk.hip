@@ -15,6 +15,7 @@
 //                  ny x nx columns (the inverse 3D DFT is separable, so its axis order is
 //                  free), which needs a quarter of the z transforms.
 #include "fft_block.hpp"
+#include "fft_general.hpp"
 #include "nlos_internal.hpp"
 #include "prec.hpp"
 
@@ -101,7 +102,7 @@ __device__ __forceinline__ PairItem pair_item(long long w, int Mx, int My) {
     it.kx = 1 + int(w / My);
     it.ky = int(w % My);
     it.kx2 = Mx - it.kx;
-    it.ky2 = (My - it.ky) & (My - 1);
+    it.ky2 = it.ky == 0 ? 0 : My - it.ky;
     it.has_mirror = true;
   } else {
     const int half = My / 2 + 1;
@@ -109,10 +110,44 @@ __device__ __forceinline__ PairItem pair_item(long long w, int Mx, int My) {
     it.kx = (w2 < half) ? 0 : Mx / 2;
     it.ky = w2 % half;
     it.kx2 = it.kx;
-    it.ky2 = (My - it.ky) & (My - 1);
+    it.ky2 = it.ky == 0 ? 0 : My - it.ky;
     it.has_mirror = (it.ky != 0) && (it.ky != My / 2);
   }
   return it;
+}
+
+// Stolt sample kz (0 <= kz < Mt) of output column (kx, ky) and of its mirror (-kx, -ky)
+// from the forward t-spectrum of column (kx, ky): q = sqrt(A + kz^2) in t-bin units
+// (A = (sxk kx)^2 + (syk ky)^2, signed kx, ky), from a float square root refined by one
+// FP64 Newton step; linear interpolation between bins floor(q) and floor(q) + 1 (the
+// last bin at the top edge itself, zero beyond it), times the Jacobian kz / q and norm.
+// The column reads bins +i (at(i)), its mirror the conjugates of bins -i (mir(i)); zero
+// unless 0 < kz < Mt/2.
+template <class At, class Mir>
+__device__ __forceinline__ void stolt_pair(int kz, int half, double A, float norm, At at, Mir mir, float2& xa,
+                                           float2& xb) {
+  xa = make_float2(0.f, 0.f);
+  xb = make_float2(0.f, 0.f);
+  if (kz > 0 && kz < half) {
+    const double q2 = A + double(kz * kz);
+    const float qf = __builtin_amdgcn_sqrtf((float)q2);
+    const float rq = __builtin_amdgcn_rcpf(qf);
+    const double q0 = (double)qf;
+    const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
+    if (q <= double(half - 1)) {
+      const double fl = floor(q);
+      const int i0 = int(fl);
+      const int i1 = i0 + 1 < half ? i0 + 1 : half - 1;
+      const float fr = float(q - fl);
+      const float jac = float(kz) * rq * norm;
+      const float2 s0 = at(i0), s1 = at(i1);
+      xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
+      xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
+      const float2 m0 = mir(i0), m1 = mir(i1);
+      xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
+      xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
+    }
+  }
 }
 
 // PADDED: the column's upper half is the zero padding (nt = N/2), known at compile time,
@@ -190,29 +225,10 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
     // a rolled loop keeps the register footprint (and so the occupancy) of the remap low
 #pragma unroll 2
     for (int kz = p; kz < a.nt; kz += P) {
-      float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
-      if (kz > 0 && kz < HALF) {
-        const double q2 = A + double(kz * kz);
-        const float qf = __builtin_amdgcn_sqrtf((float)q2);
-        const float rq = __builtin_amdgcn_rcpf(qf);
-        const double q0 = (double)qf;
-        const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
-        if (q <= double(HALF - 1)) {
-          const double fl = floor(q);
-          const int i0 = int(fl);
-          const int i1 = i0 + 1 < HALF ? i0 + 1 : HALF - 1;
-          const float fr = float(q - fl);
-          const float jac = float(kz) * rq * a.norm;
-          // column (kx, ky): samples i0, i1 of the w >= 0 half
-          const float2 s0 = my[swz(i0)], s1 = my[swz(i1)];
-          xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
-          xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
-          // mirror (-kx, -ky): conj of samples -i0, -i1 (mod N)
-          const float2 m0 = my[swz((N - i0) & (N - 1))], m1 = my[swz((N - i1) & (N - 1))];
-          xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
-          xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
-        }
-      }
+      float2 xa, xb;
+      stolt_pair(
+          kz, HALF, A, a.norm, [&](int i) { return my[swz(i)]; },
+          [&](int i) { return my[swz((N - i) & (N - 1))]; }, xa, xb);
       if constexpr (SP == SP_F16) {
         xa = ldexp2(xa, ex);
         xb = ldexp2(xb, ex);
@@ -506,6 +522,59 @@ hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, h
   if (sp == SP_F16) return launch_pair_sp<SP_F16>(n, a, tw, s);
   if (sp == SP_BF16) return launch_pair_sp<SP_BF16>(n, a, tw, s);
   return launch_pair_sp<SP_F32>(n, a, tw, s);
+}
+
+// ---------------------------------------------------------------------------
+// pass 3 for general Mt (FP32): the same column pairs and Stolt remap, the t-FFT in LDS
+// ---------------------------------------------------------------------------
+
+template <int EMAX>
+__global__ __launch_bounds__(512) void gen_column_pair(FkPairArgs a, GenPlan g, int lp) {
+  extern __shared__ float2 glds[];
+  const int N = g.n, half = N / 2, P = 1 << lp, L = blockDim.x >> lp;
+  const int tid = threadIdx.x;
+  const int l = tid >> lp, p = tid & (P - 1);
+  float2* my = glds + l * N;
+  const long long ngroups = (a.nwork + L - 1) / L;
+  for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const long long w = grp * L + l;
+    const bool ok = w < a.nwork;
+    const PairItem it = pair_item(ok ? w : 0, a.Mx, a.My);
+    const float2* in = static_cast<const float2*>(a.in) + (long long)it.ky * a.in_row + (long long)it.kx * a.nt;
+    __syncthreads();  // the previous item's last LDS reads are done
+    for (int i = p; i < N; i += P) my[i] = (ok && i < a.nt) ? in[i] : make_float2(0.f, 0.f);
+    __syncthreads();
+    gen_fft<EMAX, false>(my, 1, g, p, P);
+    const int kxs = it.kx < a.Mx / 2 ? it.kx : it.kx - a.Mx;
+    const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
+    const double ax = a.sxk * kxs, ay = a.syk * kys;
+    const double A = ax * ax + ay * ay;
+    float2* out = static_cast<float2*>(a.out);
+    const long long dst = (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
+    const long long dst2 = (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt;
+    const bool ok2 = ok && it.has_mirror;
+    for (int kz = p; kz < a.nt; kz += P) {
+      float2 xa, xb;
+      stolt_pair(
+          kz, half, A, a.norm, [&](int i) { return my[i]; }, [&](int i) { return my[i == 0 ? 0 : N - i]; }, xa,
+          xb);
+      if (ok) out[dst + kz] = xa;
+      if (ok2) out[dst2 + kz] = xb;
+    }
+  }
+}
+
+hipError_t launch_gen_column_pair(const GenPlan& g, const FkPairArgs& a, hipStream_t s) {
+  if (a.nwork <= 0 || a.nt > g.n || a.tscale_in != 0.f) return hipErrorInvalidValue;
+  int lp = 0;  // threads per column: a power of two with at most 8 samples per thread
+  while ((8 << lp) < g.n) ++lp;
+  if ((1 << lp) > 512) return hipErrorInvalidValue;
+  const int L = (1 << lp) >= 256 ? 1 : 256 >> lp;
+  const long long groups = (a.nwork + L - 1) / L;
+  const unsigned grid = (unsigned)(groups < 8192 ? groups : 8192);
+  const size_t lds = (size_t)L * g.n * sizeof(float2);
+  hipLaunchKernelGGL((gen_column_pair<8>), dim3(grid), dim3(L << lp), lds, s, a, g, lp);
+  return hipGetLastError();
 }
 
 }  // namespace nlos

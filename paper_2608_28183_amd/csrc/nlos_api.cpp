@@ -31,6 +31,17 @@ bool is_pow2_in(long long n, long long lo, long long hi) {
   return n >= lo && n <= hi && (n & (n - 1)) == 0;
 }
 
+// A padded FFT length runs on the power-of-two kernels (8 .. 2048) or on the general
+// mixed-radix ones (even, 8 .. 4096, prime factors 2, 3, 5, 7, 11, 13; FP32 only).
+bool is_general_len(long long n) {
+  nlos::GenPlan g;
+  return !is_pow2_in(n, 8, 2048) && n >= 8 && n <= nlos::kGenMaxN && nlos::gen_plan_radices((int)n, &g);
+}
+bool fk_all_pow2(const nlos_fk_desc* d) {
+  const long long p = d->pad;
+  return is_pow2_in(p * d->nx, 8, 2048) && is_pow2_in(p * d->ny, 8, 2048) && is_pow2_in(p * d->nt, 8, 2048);
+}
+
 // Elements between consecutive y (or ky) rows of the f-k intermediates: Mx * nt plus
 // 256 bytes, so that the y passes, which step through rows, do not hit the same
 // memory channels at a power-of-two stride.  es is the bytes per complex element.
@@ -101,6 +112,12 @@ struct nlos_fk_plan {
   int Mx = 0, My = 0, Mt = 0;
   double sxk = 0, syk = 0;
   float norm = 0.f;
+  // general (not power-of-two) axis lengths: radix plans and their W_M^k tables, which
+  // live in d_gtw.  gen_xr2c: the x pass runs on the general kernel, also for a
+  // power-of-two Mx when nt is odd (the tuned kernel packs t-column pairs as float2).
+  bool gen_x = false, gen_y = false, gen_t = false, gen_xr2c = false;
+  nlos::GenPlan gx{}, gy{}, gt{};
+  float2* d_gtw = nullptr;
 };
 
 struct nlos_rsd_plan {
@@ -466,10 +483,16 @@ nlos_status nlos_fk_check(const nlos_fk_desc* d) {
   if (d->prec != NLOS_FP32 && d->prec != NLOS_FP16 && d->prec != NLOS_BF16)
     return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bad precision %d", (int)d->prec);
   const long long p = d->pad;
-  if (!is_pow2_in(p * d->nx, 8, 2048) || !is_pow2_in(p * d->ny, 8, 2048) ||
-      !is_pow2_in(p * d->nt, 8, 2048))
+  if (fk_all_pow2(d)) return NLOS_OK;
+  for (long long m : {p * d->nx, p * d->ny, p * d->nt})
+    if (!is_pow2_in(m, 8, 2048) && !is_general_len(m))
+      return fail(nullptr, NLOS_ERR_UNSUPPORTED,
+                  "fk: padded sizes %lld x %lld x %lld must be powers of two in [8, 2048] or even lengths "
+                  "in [8, 4096] with prime factors 2, 3, 5, 7, 11, 13",
+                  p * d->ny, p * d->nx, p * d->nt);
+  if (d->prec != NLOS_FP32)
     return fail(nullptr, NLOS_ERR_UNSUPPORTED,
-                "fk: padded sizes %lld x %lld x %lld must be powers of two in [8, 2048]", p * d->ny,
+                "fk: FP16 / BF16 storage needs power-of-two padded sizes (%lld x %lld x %lld)", p * d->ny,
                 p * d->nx, p * d->nt);
   return NLOS_OK;
 }
@@ -499,11 +522,51 @@ nlos_status nlos_fk_plan_create(nlos_ctx* ctx, const nlos_fk_desc* d, nlos_fk_pl
   p->sxk = sx * (double)p->Mt / (double)p->Mx;
   p->syk = sy * (double)p->Mt / (double)p->My;
   p->norm = (float)(1.0 / ((double)p->Mx * (double)p->My * (double)p->Mt));
+  // general axis lengths: radix plans and W_M^k = exp(-2 pi i k / M) tables (FP64, exact
+  // octant reduction, stored as float), one allocation for the three axes
+  struct Axis { int m; bool* on; nlos::GenPlan* g; } axes[3] = {
+      {p->Mx, &p->gen_x, &p->gx}, {p->My, &p->gen_y, &p->gy}, {p->Mt, &p->gen_t, &p->gt}};
+  std::vector<float2> tw;
+  std::vector<size_t> off(3, 0);
+  const bool odd_nt = (d->nt & 1) != 0;
+  for (int i = 0; i < 3; ++i) {
+    if (is_pow2_in(axes[i].m, 8, 2048) && !(i == 0 && odd_nt)) continue;
+    if (!nlos::gen_plan_radices(axes[i].m, axes[i].g)) {
+      delete p;
+      return fail(ctx, NLOS_ERR_INTERNAL, "fk_plan_create: no radix plan for %d", axes[i].m);
+    }
+    *axes[i].on = !is_pow2_in(axes[i].m, 8, 2048);
+    if (i == 0) p->gen_xr2c = true;
+    off[i] = tw.size();
+    for (int k = 0; k < axes[i].m; ++k) {
+      double cs, sn;
+      nlos::cos_sin_2pi_frac(k, axes[i].m, &cs, &sn);
+      tw.push_back(make_float2((float)cs, (float)-sn));
+    }
+  }
+  if (!tw.empty()) {
+    if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&p->d_gtw, tw.size() * sizeof(float2)) != hipSuccess) {
+      delete p;
+      return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "fk_plan_create: twiddle table allocation");
+    }
+    if (hipMemcpy(p->d_gtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(p->d_gtw);
+      delete p;
+      return fail(ctx, NLOS_ERR_DEVICE, "fk_plan_create: twiddle upload failed");
+    }
+    for (int i = 0; i < 3; ++i)
+      if (*axes[i].on || (i == 0 && p->gen_xr2c)) axes[i].g->tw = p->d_gtw + off[i];
+  }
   *out = p;
   return NLOS_OK;
 }
 
 nlos_status nlos_fk_plan_destroy(nlos_fk_plan* p) {
+  if (!p) return NLOS_OK;
+  if (p->d_gtw) {
+    (void)hipSetDevice(p->device);
+    (void)hipFree(p->d_gtw);
+  }
   delete p;
   return NLOS_OK;
 }
@@ -547,14 +610,19 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   x.tau = d_tau; x.out = W1; x.out_plane = RH; x.nx = (int)nx; x.nt = (int)nt;
   x.tscale = (float)(1.0 / (double)(nt - 1));
   x.e_out = ex;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_X, [&] { return nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_X, [&] {
+    return p->gen_xr2c ? nlos::launch_gen_xr2c(p->gx, x, (int)ny, s) : nlos::launch_fk_xr2c((int)Mx, x, (int)ny, tw, s, sp);
+  }));
   // pass 2: y-FFT of the Mx/2 + 1 planes, zero padded to My
   StridedArgs a{};
   a.in = W1; a.out = W2;
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
   a.e_in = ex; a.e_out = ex;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp, true); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] {
+    return p->gen_y ? nlos::launch_gen_strided(p->gy, false, nlos::ST_C64, a, (int)(Mx / 2 + 1), s)
+                    : nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp, true);
+  }));
   // pass 3: per column of the half spectrum: t-FFT, Stolt + Jacobian + 1/(Mx My Mt) for the
   // column and its mirror; the remapped spectra (kz < nt) go to W3
   FkPairArgs c{};
@@ -563,21 +631,29 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   c.nt = (int)nt; c.Mx = (int)Mx; c.My = (int)My;
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
   c.e_in = ex; c.e_out = ex ? ex + 1 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] { return nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] {
+    return p->gen_t ? nlos::launch_gen_column_pair(p->gt, c, s) : nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp);
+  }));
   // pass 4: y-IFFT, keep y < ny
   a = StridedArgs{};
   a.in = W3; a.out = W4;
   a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
+    return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
+                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true);
+  }));
   // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
   a = StridedArgs{};
   a.in = W4; a.out = W5;
   a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
+    return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)ny, s)
+                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true);
+  }));
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
@@ -586,10 +662,16 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   z.e_in = ex ? ex + 3 : nullptr;
   if (d_psi) {  // the complex field Psi itself (FP32 path)
     z.out = d_psi; z.img = nullptr;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_C64, z, tw, s); }));
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] {
+      return p->gen_t ? nlos::launch_gen_contig(p->gt, true, nlos::CL_C64, nlos::CS_C64, z, s)
+                      : nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_C64, z, tw, s);
+    }));
     return NLOS_OK;
   }
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] { return nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] {
+    return p->gen_t ? nlos::launch_gen_contig(p->gt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, s)
+                    : nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp);
+  }));
   return NLOS_OK;
 }
 
@@ -1013,6 +1095,8 @@ nlos_status nlos_moe_check(const nlos_fk_desc* fk, const nlos_rsd_desc* rsd, dou
                 "moe: the f-k and RSD descriptors must describe the same transient and grid");
   if (fk->prec != NLOS_FP32 || rsd->data_prec != NLOS_FP32)
     return fail(nullptr, NLOS_ERR_UNSUPPORTED, "moe: FP32 intermediates only");
+  if (!fk_all_pow2(fk))
+    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "moe: power-of-two padded sizes only");
   if (!(beta >= 0.0) || !std::isfinite(beta) || !(eps > 0.0) || !std::isfinite(eps))
     return fail(nullptr, NLOS_ERR_INVALID_ARG, "moe: need beta >= 0 and eps > 0, finite");
   return NLOS_OK;

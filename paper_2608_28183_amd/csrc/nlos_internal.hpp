@@ -113,6 +113,26 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
                          const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hipStream_t s, int sp = 0);
 hipError_t launch_fk_column_pair(int n, const FkPairArgs& a, const float2* tw, hipStream_t s, int sp = 0);
+
+// General-length lines (FP32 only): n even, n <= kGenMaxN, prime factors 2, 3, 5, 7, 11,
+// 13; the radices of the Stockham stages and a table of W_n^k (k < n, FP64-generated).
+constexpr int kGenMaxStages = 12;
+constexpr int kGenMaxN = 4096;
+struct GenPlan {
+  int n, nstage;
+  int radix[kGenMaxStages];
+  const float2* tw;  // device, W_n^k = exp(-2 pi i k / n), k in [0, n)
+};
+// host: radix plan of n (tw left null); false when n is not supported
+bool gen_plan_radices(int n, GenPlan* g);
+// the same passes as launch_strided (LD_C64 with ST_C64, ST_C64_SCALED or ST_ABS_IMG),
+// launch_contig (CL_C64 or CL_REAL with CS_C64, CS_ABS2_MAX, CS_BINS or CS_ABS_IMG),
+// launch_fk_xr2c and launch_fk_column_pair (no input t-scaling), for lines of length g.n
+hipError_t launch_gen_strided(const GenPlan& g, bool inverse, int st, const StridedArgs& a, int nplanes,
+                              hipStream_t s);
+hipError_t launch_gen_contig(const GenPlan& g, bool inverse, int ld, int st, const ContigArgs& a, hipStream_t s);
+hipError_t launch_gen_xr2c(const GenPlan& g, const FkXArgs& a, int ny, hipStream_t s);
+hipError_t launch_gen_column_pair(const GenPlan& g, const FkPairArgs& a, hipStream_t s);
 hipError_t launch_moe_phasor_pair(const MoePhasorArgs& a, const float2* tw, hipStream_t s);
 // coherence-weighted merging over a ring of `window` complex frames of n values:
 // writes `frame` into ring slot `slot`, then sums the `count` most recent frames (ring

@@ -21,6 +21,8 @@ struct Stor;
 // ld(p, i) loads and converts; readers that load many values under conditions use
 // raw(p, i) (the stored bits, R) inside the condition and cvt(R) after all loads, so
 // that the loads stay in flight together instead of each waiting for its conversion.
+// The four-byte forms hold only f-k volumes, which every pass streams once: their
+// loads and stores are non-temporal.
 template <>
 struct Stor<SP_F32> {
   using T = float2;
@@ -45,7 +47,7 @@ struct Stor<SP_F16> {
   using R = unsigned int;
   static __device__ __forceinline__ R zero() { return 0u; }
   static __device__ __forceinline__ R raw(const T* p, long long i) {
-    return reinterpret_cast<const unsigned int*>(p)[i];
+    return __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p) + i);
   }
   static __device__ __forceinline__ float2 cvt(R r) {
     const nlos_h2 h = __builtin_bit_cast(nlos_h2, r);
@@ -57,11 +59,13 @@ struct Stor<SP_F16> {
     return __builtin_bit_cast(unsigned int, h);
   }
   static __device__ __forceinline__ void st(T* p, long long i, float2 v) {
-    reinterpret_cast<unsigned int*>(p)[i] = pack(v);
+    __builtin_nontemporal_store(pack(v), reinterpret_cast<unsigned int*>(p) + i);
   }
   // two consecutive values (i even: one 8-byte store)
   static __device__ __forceinline__ void st2(T* p, long long i, float2 a, float2 b) {
-    *reinterpret_cast<uint2*>(p + i) = make_uint2(pack(a), pack(b));
+    typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+    const u2v w = {pack(a), pack(b)};
+    __builtin_nontemporal_store(w, reinterpret_cast<u2v*>(p + i));
   }
 };
 
@@ -71,7 +75,7 @@ struct Stor<SP_BF16> {
   using R = unsigned int;
   static __device__ __forceinline__ R zero() { return 0u; }
   static __device__ __forceinline__ R raw(const T* p, long long i) {
-    return reinterpret_cast<const unsigned int*>(p)[i];
+    return __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p) + i);
   }
   // a bfloat16 is the upper half of the float with the same bits
   static __device__ __forceinline__ float2 cvt(R r) {
@@ -84,11 +88,13 @@ struct Stor<SP_BF16> {
     return __builtin_bit_cast(unsigned int, h);
   }
   static __device__ __forceinline__ void st(T* p, long long i, float2 v) {
-    reinterpret_cast<unsigned int*>(p)[i] = pack(v);
+    __builtin_nontemporal_store(pack(v), reinterpret_cast<unsigned int*>(p) + i);
   }
   // two consecutive values (i even: one 8-byte store)
   static __device__ __forceinline__ void st2(T* p, long long i, float2 a, float2 b) {
-    *reinterpret_cast<uint2*>(p + i) = make_uint2(pack(a), pack(b));
+    typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+    const u2v w = {pack(a), pack(b)};
+    __builtin_nontemporal_store(w, reinterpret_cast<u2v*>(p + i));
   }
 };
 

@@ -34,8 +34,18 @@ def test_fk_validation():
     ok = nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=2)
     assert nlos.nlos_fk_check(ok) == nlos.NLOS_OK
     assert nlos.nlos_fk_check(nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=3)) == nlos.NLOS_ERR_INVALID_ARG
-    assert nlos.nlos_fk_check(nlos.fk_desc(100, 256, 512, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
-    assert nlos.nlos_fk_check(nlos.fk_desc(2048, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    # general lengths: even, prime factors up to 13, at most 4096, FP32 storage only
+    assert nlos.nlos_fk_check(nlos.fk_desc(100, 256, 512, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(260, 360, 512, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(260, 360, 1500, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(260, 360, 375, 1.0, 1.0, 32.0, pad=1)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(17, 16, 16, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(8, 8, 2500, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(100, 256, 512, 1.0, 1.0, 32.0, prec="fp16")) == nlos.NLOS_ERR_UNSUPPORTED
+    assert nlos.nlos_fk_check(nlos.fk_desc(100, 256, 512, 1.0, 1.0, 32.0, prec="bf16")) == nlos.NLOS_ERR_UNSUPPORTED
+    # 4096 exceeds the power-of-two kernels and runs on the general ones; 4100 exceeds both
+    assert nlos.nlos_fk_check(nlos.fk_desc(2048, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
+    assert nlos.nlos_fk_check(nlos.fk_desc(2050, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
     assert nlos.nlos_fk_check(nlos.fk_desc(1024, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_OK
     assert nlos.nlos_fk_check(nlos.fk_desc(2, 8, 8, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_UNSUPPORTED
     assert nlos.nlos_fk_check(nlos.fk_desc(8, 8, 1, 1.0, 1.0, 32.0)) == nlos.NLOS_ERR_INVALID_ARG

@@ -87,6 +87,40 @@ def test_stolt_jacobian_is_a_change_of_variables():
         assert abs(total - exact) < 2e-3 * exact
 
 
+def test_dft_mixed_radix_lengths_brute_force():
+    """Padded lengths with factors 3, 5, 7 (6 x 10 x 14): the same triple sum."""
+    rng = np.random.default_rng(3)
+    tau = rng.poisson(3.0, size=(3, 5, 7)).astype(np.float64)
+    G = ofk.scale_and_pad(tau, 2)
+    S = ofk.forward(G)
+    My, Mx, Mt = S.shape
+    assert (My, Mx, Mt) == (6, 10, 14)
+    g = G[:3, :5, :7]
+    ref = np.zeros(S.shape, dtype=np.complex128)
+    for a in range(My):
+        for b in range(Mx):
+            for c in range(Mt):
+                ph = ((a * np.arange(3))[:, None, None] * Mx * Mt + (b * np.arange(5))[None, :, None] * My * Mt
+                      + (c * np.arange(7))[None, None, :] * My * Mx) % (My * Mx * Mt)
+                ref[a, b, c] = np.sum(g * np.exp(-2j * np.pi * ph / (My * Mx * Mt)))
+    assert np.max(np.abs(S - ref)) < 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(S - np.fft.fftn(G))) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_point_reflector_focuses_on_a_mixed_radix_grid():
+    """A 30 x 26 scan of 192 bins pads to 60 x 52 x 384 (factors 3, 5, 13)."""
+    cfg = scenes.small_config(30, 26, 192, bin_ps=32)
+    pos = (0.1, -0.2, 0.5)
+    tau = scenes.transient(cfg, noise=False, objects=[scenes.point_object(*pos)])
+    vol, img = ofk.fk(tau, 1.0, 1.0, 32.0, pad=2)
+    y, x, z = argmax_index(vol)
+    ex = (pos[0] + 0.5) / cfg.dx - 0.5
+    ey = (pos[1] + 0.5) / cfg.dy - 0.5
+    ez = 2.0 * pos[2] / cfg.c_dt
+    assert abs(x - ex) <= 1 and abs(y - ey) <= 1 and abs(z - ez) <= 1
+    assert argmax_index(img) == (y, x)
+
+
 @pytest.mark.parametrize("pos", [(0.1, -0.2, 0.5), (-0.3, 0.25, 0.7)])
 def test_point_reflector_focuses_at_closed_form(pos):
     cfg = scenes.small_config(32, 32, 256, bin_ps=32)
