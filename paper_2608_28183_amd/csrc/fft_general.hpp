@@ -66,12 +66,20 @@ __device__ __forceinline__ void dft_any(float2* v) {
   }
 }
 
+// LDS pointers typed as such (address space 3): the stages are not inlined, and through
+// a plain pointer their accesses would compile to flat instructions instead of ds_ ones.
+typedef float nlos_v2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) nlos_v2 lds_v2;
+__device__ __forceinline__ lds_v2* as_lds(float2* p) { return (lds_v2*)p; }
+__device__ __forceinline__ const lds_v2* as_lds(const float2* p) { return (const lds_v2*)p; }
+
 // One stage on a line at base[i * ls], i < n, shared by P threads (thread p).  Every
 // thread of the block calls it (it synchronises the block); Q bounds the butterflies per
-// thread, so Q * P >= n / R must hold.
+// thread, so Q * P >= n / R must hold.  Not inlined: each radix then gets its own register
+// allocation instead of the union over the dispatch in gen_fft.
 template <int R, int Q, bool INV>
-__device__ __forceinline__ void gen_stage(float2* base, int ls, int n, int ns, int p, int P,
-                                          const float2* __restrict__ tw) {
+__device__ __attribute__((noinline)) void gen_stage(lds_v2* base, int ls, int n, int ns, int p, int P,
+                                                   const lds_v2* tw) {
   const int nb = n / R;
   float2 v[Q][R];
   static_for<Q>([&](auto q_) {
@@ -80,7 +88,8 @@ __device__ __forceinline__ void gen_stage(float2* base, int ls, int n, int ns, i
     if (j < nb) {
       static_for<R>([&](auto r_) {
         constexpr int r = decltype(r_)::value;
-        v[q][r] = base[(j + r * nb) * ls];
+        const nlos_v2 t = base[(j + r * nb) * ls];
+        v[q][r] = make_float2(t.x, t.y);
       });
     }
   });
@@ -94,8 +103,8 @@ __device__ __forceinline__ void gen_stage(float2* base, int ls, int n, int ns, i
       if (ns > 1) {
         static_for<R - 1>([&](auto r_) {
           constexpr int r = decltype(r_)::value + 1;
-          float2 w = tw[jm * r * step];
-          if (INV) w.y = -w.y;
+          const nlos_v2 t = tw[jm * r * step];
+          const float2 w = make_float2(t.x, INV ? -t.y : t.y);
           v[q][r] = cmul(v[q][r], w);
         });
       }
@@ -103,7 +112,7 @@ __device__ __forceinline__ void gen_stage(float2* base, int ls, int n, int ns, i
       const int o = (j - jm) * R + jm;
       static_for<R>([&](auto r_) {
         constexpr int r = decltype(r_)::value;
-        base[(o + r * ns) * ls] = v[q][r];
+        base[(o + r * ns) * ls] = nlos_v2{v[q][r].x, v[q][r].y};
       });
     }
   });
@@ -112,22 +121,31 @@ __device__ __forceinline__ void gen_stage(float2* base, int ls, int n, int ns, i
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// The block's copy of the twiddle table in LDS (read before the first stage's barrier):
+// a stage then waits on LDS, not on a gather from L2.
+__device__ __forceinline__ void gen_load_twiddles(float2* twl, const GenPlan& g) {
+  for (int k = threadIdx.x; k < g.n; k += blockDim.x) twl[k] = g.tw[k];
+}
+
 // Whole transform of the line at base[i * ls] in place, natural order in and out
-// (unnormalised both ways).  EMAX bounds the samples per thread: EMAX * P >= g.n.
+// (unnormalised both ways).  EMAX bounds the samples per thread: EMAX * P >= g.n.  tw is
+// the block's LDS copy of g.tw (gen_load_twiddles).
 template <int EMAX, bool INV>
-__device__ __forceinline__ void gen_fft(float2* base, int ls, const GenPlan& g, int p, int P) {
+__device__ __forceinline__ void gen_fft(float2* line, int ls, const GenPlan& g, const float2* twl, int p, int P) {
+  lds_v2* base = as_lds(line);
+  const lds_v2* tw = as_lds(twl);
   int ns = 1;
   for (int s = 0; s < g.nstage; ++s) {
     const int R = g.radix[s];
     switch (R) {
-      case 2: gen_stage<2, cdiv(EMAX, 2), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 3: gen_stage<3, cdiv(EMAX, 3), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 4: gen_stage<4, cdiv(EMAX, 4), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 5: gen_stage<5, cdiv(EMAX, 5), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 7: gen_stage<7, cdiv(EMAX, 7), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 8: gen_stage<8, cdiv(EMAX, 8), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 11: gen_stage<11, cdiv(EMAX, 11), INV>(base, ls, g.n, ns, p, P, g.tw); break;
-      case 13: gen_stage<13, cdiv(EMAX, 13), INV>(base, ls, g.n, ns, p, P, g.tw); break;
+      case 2: gen_stage<2, cdiv(EMAX, 2), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 3: gen_stage<3, cdiv(EMAX, 3), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 4: gen_stage<4, cdiv(EMAX, 4), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 5: gen_stage<5, cdiv(EMAX, 5), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 7: gen_stage<7, cdiv(EMAX, 7), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 8: gen_stage<8, cdiv(EMAX, 8), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 11: gen_stage<11, cdiv(EMAX, 11), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 13: gen_stage<13, cdiv(EMAX, 13), INV>(base, ls, g.n, ns, p, P, tw); break;
       default: break;  // the host plans only the radices above
     }
     ns *= R;

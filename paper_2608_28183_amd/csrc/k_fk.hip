@@ -535,16 +535,28 @@ __global__ __launch_bounds__(512) void gen_column_pair(FkPairArgs a, GenPlan g, 
   const int tid = threadIdx.x;
   const int l = tid >> lp, p = tid & (P - 1);
   float2* my = glds + l * N;
+  float2* twl = glds + L * N;
+  gen_load_twiddles(twl, g);  // read after the first barrier of the loop
   const long long ngroups = (a.nwork + L - 1) / L;
   for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const long long w = grp * L + l;
     const bool ok = w < a.nwork;
     const PairItem it = pair_item(ok ? w : 0, a.Mx, a.My);
     const float2* in = static_cast<const float2*>(a.in) + (long long)it.ky * a.in_row + (long long)it.kx * a.nt;
+    float2 x[EMAX];  // all loads in flight before any LDS write (EMAX * P >= N)
+    static_for<EMAX>([&](auto k_) {
+      constexpr int k = decltype(k_)::value;
+      const int i = p + k * P;
+      x[k] = (ok && i < a.nt) ? in[i] : make_float2(0.f, 0.f);
+    });
     __syncthreads();  // the previous item's last LDS reads are done
-    for (int i = p; i < N; i += P) my[i] = (ok && i < a.nt) ? in[i] : make_float2(0.f, 0.f);
+    static_for<EMAX>([&](auto k_) {
+      constexpr int k = decltype(k_)::value;
+      const int i = p + k * P;
+      if (i < N) my[i] = x[k];
+    });
     __syncthreads();
-    gen_fft<EMAX, false>(my, 1, g, p, P);
+    gen_fft<EMAX, false>(my, 1, g, twl, p, P);
     const int kxs = it.kx < a.Mx / 2 ? it.kx : it.kx - a.Mx;
     const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
     const double ax = a.sxk * kxs, ay = a.syk * kys;
@@ -572,7 +584,7 @@ hipError_t launch_gen_column_pair(const GenPlan& g, const FkPairArgs& a, hipStre
   const int L = (1 << lp) >= 256 ? 1 : 256 >> lp;
   const long long groups = (a.nwork + L - 1) / L;
   const unsigned grid = (unsigned)(groups < 8192 ? groups : 8192);
-  const size_t lds = (size_t)L * g.n * sizeof(float2);
+  const size_t lds = (size_t)(L + 1) * g.n * sizeof(float2);
   hipLaunchKernelGGL((gen_column_pair<8>), dim3(grid), dim3(L << lp), lds, s, a, g, lp);
   return hipGetLastError();
 }

@@ -19,10 +19,10 @@ constexpr int kGenMaxThreads = 1024;
 int gen_line_threads(int n) { return (n + kGenE - 1) / kGenE; }
 
 // columns per block of a strided pass: up to a 16-column (128-byte) row segment, within
-// 64 KiB of LDS and 1024 threads
+// 64 KiB of LDS (the tile and the twiddle table) and 1024 threads
 int gen_cols(int n) {
   int t = 16;
-  while (t > 1 && ((long long)n * t * (long long)sizeof(float2) > 65536 || t * gen_line_threads(n) > kGenMaxThreads))
+  while (t > 1 && ((long long)n * (t + 1) * (long long)sizeof(float2) > 65536 || t * gen_line_threads(n) > kGenMaxThreads))
     t >>= 1;
   return t;
 }
@@ -39,6 +39,15 @@ int ilog2i(int v) {
 // strided lines: tile of T adjacent columns, LDS [n][T]
 // ---------------------------------------------------------------------------
 
+// Tile of a block, XCD-aware: blocks b and b + 8 run on one XCD (blocks go round-robin
+// over the 8 XCDs), so within each 16 blocks they take the tiles 2k and 2k + 1, whose
+// 64-byte row segments share 128-byte lines, and the second finds the lines in that L2.
+__device__ __forceinline__ int gen_tile() {
+  const int b = blockIdx.x;
+  return (gridDim.x % 16 == 0) ? ((b & ~15) | ((b & 7) << 1) | ((b >> 3) & 1)) : b;
+}
+
+
 template <int EMAX, bool INV, int ST>
 __global__ __launch_bounds__(kGenMaxThreads) void gen_strided(StridedArgs a, GenPlan g, int lt) {
   extern __shared__ float2 glds[];
@@ -46,17 +55,28 @@ __global__ __launch_bounds__(kGenMaxThreads) void gen_strided(StridedArgs a, Gen
   const int tid = threadIdx.x;
   const int c = tid & (T - 1), p = tid >> lt;
   const long long plane = blockIdx.y;
-  const int col = blockIdx.x * T + c;
+  const int col = gen_tile() * T + c;
   const bool colok = col < a.ncols;
   const float2* in = static_cast<const float2*>(a.in) + plane * a.in_plane + (colok ? col : 0);
-  for (int i = p; i < n; i += P) {
-    float2 x = make_float2(0.f, 0.f);
-    if (colok && i < a.n_in) x = in[(long long)i * a.in_line];
-    glds[i * T + c] = x;
-  }
+  // samples i = p + k P (k < EMAX cover the line): all loads in flight before any LDS write
+  float2 x[EMAX];
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    x[k] = (colok && i < a.n_in) ? in[(long long)i * a.in_line] : make_float2(0.f, 0.f);
+  });
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    if (i < n) glds[i * T + c] = x[k];
+  });
+  float2* twl = glds + n * T;
+  gen_load_twiddles(twl, g);
   __syncthreads();
-  gen_fft<EMAX, INV>(glds + c, T, g, p, P);
-  for (int i = p; i < a.n_out; i += P) {
+  gen_fft<EMAX, INV>(glds + c, T, g, twl, p, P);
+  static_for<EMAX>([&](auto k_) {
+    const int i = p + decltype(k_)::value * P;
+    if (i >= a.n_out) return;
     const float2 v = glds[i * T + c];
     if constexpr (ST == ST_C64 || ST == ST_C64_SCALED) {
       if (colok)
@@ -67,13 +87,13 @@ __global__ __launch_bounds__(kGenMaxThreads) void gen_strided(StridedArgs a, Gen
       if (a.out != nullptr && colok)
         static_cast<float*>(a.out)[plane * a.out_plane + (long long)i * a.out_line + col] = m;
       if (a.img != nullptr) {
-        // the T lanes of one row are adjacent in the wave and run the same iterations
+        // the T lanes of one row are adjacent in the wave and take the same branches
         for (int off = 1; off < T; off <<= 1) m = fmaxf(m, __shfl_xor(m, off, T));
         if (c == 0)
           atomicMax(reinterpret_cast<unsigned int*>(a.img) + plane * a.img_plane + i, __float_as_uint(m));
       }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -89,18 +109,27 @@ __global__ __launch_bounds__(kGenMaxThreads) void gen_contig(ContigArgs a, GenPl
   const long long line = (long long)blockIdx.x * L + l;
   const bool lineok = line < a.nlines;
   float2* my = glds + l * n;
-  for (int i = p; i < n; i += P) {
-    float2 x = make_float2(0.f, 0.f);
+  float2 x[EMAX];
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    x[k] = make_float2(0.f, 0.f);
     if (lineok && i < a.n_in) {
       if constexpr (LD == CL_REAL)
-        x.x = static_cast<const float*>(a.in)[line * a.in_line + i];
+        x[k].x = static_cast<const float*>(a.in)[line * a.in_line + i];
       else
-        x = static_cast<const float2*>(a.in)[line * a.in_line + i];
+        x[k] = static_cast<const float2*>(a.in)[line * a.in_line + i];
     }
-    my[i] = x;
-  }
+  });
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    if (i < n) my[i] = x[k];
+  });
+  float2* twl = glds + L * n;
+  gen_load_twiddles(twl, g);
   __syncthreads();
-  gen_fft<EMAX, INV>(my, 1, g, p, P);
+  gen_fft<EMAX, INV>(my, 1, g, twl, p, P);
   if constexpr (ST == CS_BINS) {
     const long long line0 = (long long)blockIdx.x * L;
     for (int k = tid; k < L * a.nbins; k += blockDim.x) {
@@ -150,21 +179,30 @@ __global__ __launch_bounds__(kGenMaxThreads) void gen_xr2c(FkXArgs a, GenPlan g,
   const int tid = threadIdx.x;
   const int c = tid & (T - 1), p = tid >> lt;
   const long long y = blockIdx.y;
-  const int t0 = 2 * (blockIdx.x * T + c);  // real columns t0 and t0 + 1
+  const int t0 = 2 * (gen_tile() * T + c);  // real columns t0 and t0 + 1
   const bool colok = t0 < a.nt, has1 = t0 + 1 < a.nt;
   const float s0 = a.unscaled ? 1.f : float(t0) * a.tscale;
   const float s1 = a.unscaled ? 1.f : float(t0 + 1) * a.tscale;
-  for (int i = p; i < n; i += P) {
-    float2 x = make_float2(0.f, 0.f);
+  float2 x[EMAX];
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    x[k] = make_float2(0.f, 0.f);
     if (colok && i < a.nx) {
       const float* row = a.tau + (y * a.nx + i) * a.nt + t0;
-      x.x = row[0] * s0;
-      if (has1) x.y = row[1] * s1;
+      x[k].x = row[0];
+      if (has1) x[k].y = row[1];
     }
-    glds[i * T + c] = x;
-  }
+  });
+  static_for<EMAX>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    const int i = p + k * P;
+    if (i < n) glds[i * T + c] = make_float2(x[k].x * s0, x[k].y * s1);
+  });
+  float2* twl = glds + n * T;
+  gen_load_twiddles(twl, g);
   __syncthreads();
-  gen_fft<EMAX, false>(glds + c, T, g, p, P);
+  gen_fft<EMAX, false>(glds + c, T, g, twl, p, P);
   if (!colok) return;
   float2* out = static_cast<float2*>(a.out) + y * a.out_plane + t0;
   for (int k = p; k <= n / 2; k += P) {
@@ -210,7 +248,7 @@ template <bool INV, int ST>
 hipError_t gen_strided_st(const GenPlan& g, const StridedArgs& a, int nplanes, hipStream_t s) {
   const int T = gen_cols(g.n), P = gen_line_threads(g.n);
   const dim3 grid((a.ncols + T - 1) / T, nplanes);
-  const size_t lds = (size_t)g.n * T * sizeof(float2);
+  const size_t lds = (size_t)g.n * (T + 1) * sizeof(float2);
   hipLaunchKernelGGL((gen_strided<kGenE, INV, ST>), grid, dim3(T * P), lds, s, a, g, ilog2i(T));
   return hipGetLastError();
 }
@@ -230,7 +268,7 @@ hipError_t gen_contig_st(const GenPlan& g, const ContigArgs& a, hipStream_t s) {
   gen_contig_shape(g.n, &lp, &L);
   const long long blocks = (a.nlines + L - 1) / L;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = (size_t)L * g.n * sizeof(float2);
+  const size_t lds = (size_t)(L + 1) * g.n * sizeof(float2);
   hipLaunchKernelGGL((gen_contig<kGenE, INV, LD, ST>), dim3((unsigned)blocks), dim3(L << lp), lds, s, a, g, lp);
   return hipGetLastError();
 }
@@ -271,7 +309,7 @@ hipError_t launch_gen_xr2c(const GenPlan& g, const FkXArgs& a, int ny, hipStream
   const int T = gen_cols(g.n), P = gen_line_threads(g.n);
   const int pairs = (a.nt + 1) / 2;
   const dim3 grid((pairs + T - 1) / T, ny);
-  const size_t lds = (size_t)g.n * T * sizeof(float2);
+  const size_t lds = (size_t)g.n * (T + 1) * sizeof(float2);
   hipLaunchKernelGGL((gen_xr2c<kGenE>), grid, dim3(T * P), lds, s, a, g, ilog2i(T));
   return hipGetLastError();
 }
