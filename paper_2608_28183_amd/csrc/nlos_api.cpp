@@ -42,6 +42,38 @@ bool fk_all_pow2(const nlos_fk_desc* d) {
   return is_pow2_in(p * d->nx, 8, 2048) && is_pow2_in(p * d->ny, 8, 2048) && is_pow2_in(p * d->nt, 8, 2048);
 }
 
+// Radix plans of the axes that run on the general kernels (use[i]) and their W_m^k =
+// exp(-2 pi i k / m) tables (FP64 with exact octant reduction, stored as float), in one
+// device allocation *d_tw (null when no axis needs one).
+hipError_t gen_tables(int device, const int* m, const bool* use, nlos::GenPlan* const* g, int naxes,
+                      float2** d_tw) {
+  std::vector<float2> tw;
+  std::vector<size_t> off(naxes, 0);
+  for (int i = 0; i < naxes; ++i) {
+    if (!use[i]) continue;
+    if (!nlos::gen_plan_radices(m[i], g[i])) return hipErrorInvalidValue;
+    off[i] = tw.size();
+    for (int k = 0; k < m[i]; ++k) {
+      double cs, sn;
+      nlos::cos_sin_2pi_frac(k, m[i], &cs, &sn);
+      tw.push_back(make_float2((float)cs, (float)-sn));
+    }
+  }
+  *d_tw = nullptr;
+  if (tw.empty()) return hipSuccess;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc(d_tw, tw.size() * sizeof(float2));
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpy(*d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(*d_tw);
+    *d_tw = nullptr;
+    return e;
+  }
+  for (int i = 0; i < naxes; ++i)
+    if (use[i]) g[i]->tw = *d_tw + off[i];
+  return hipSuccess;
+}
+
 // Elements between consecutive y (or ky) rows of the f-k intermediates: Mx * nt plus
 // 256 bytes, so that the y passes, which step through rows, do not hit the same
 // memory channels at a power-of-two stride.  es is the bytes per complex element.
@@ -133,6 +165,11 @@ struct nlos_rsd_plan {
   float* d_chunk_wa = nullptr;
   float* d_chunk_wb = nullptr;
   long long nchunks = 0;
+  // general (not power-of-two) lengths of the x, y and phasor t transforms: radix plans
+  // and W_m^k tables (in d_gtw)
+  bool gen_x = false, gen_y = false, gen_t = false;
+  nlos::GenPlan gx{}, gy{}, gt{};
+  float2* d_gtw = nullptr;
 };
 
 static nlos_status fail(nlos_ctx* ctx, nlos_status s, const char* fmt, ...) {
@@ -522,40 +559,19 @@ nlos_status nlos_fk_plan_create(nlos_ctx* ctx, const nlos_fk_desc* d, nlos_fk_pl
   p->sxk = sx * (double)p->Mt / (double)p->Mx;
   p->syk = sy * (double)p->Mt / (double)p->My;
   p->norm = (float)(1.0 / ((double)p->Mx * (double)p->My * (double)p->Mt));
-  // general axis lengths: radix plans and W_M^k = exp(-2 pi i k / M) tables (FP64, exact
-  // octant reduction, stored as float), one allocation for the three axes
-  struct Axis { int m; bool* on; nlos::GenPlan* g; } axes[3] = {
-      {p->Mx, &p->gen_x, &p->gx}, {p->My, &p->gen_y, &p->gy}, {p->Mt, &p->gen_t, &p->gt}};
-  std::vector<float2> tw;
-  std::vector<size_t> off(3, 0);
-  const bool odd_nt = (d->nt & 1) != 0;
-  for (int i = 0; i < 3; ++i) {
-    if (is_pow2_in(axes[i].m, 8, 2048) && !(i == 0 && odd_nt)) continue;
-    if (!nlos::gen_plan_radices(axes[i].m, axes[i].g)) {
-      delete p;
-      return fail(ctx, NLOS_ERR_INTERNAL, "fk_plan_create: no radix plan for %d", axes[i].m);
-    }
-    *axes[i].on = !is_pow2_in(axes[i].m, 8, 2048);
-    if (i == 0) p->gen_xr2c = true;
-    off[i] = tw.size();
-    for (int k = 0; k < axes[i].m; ++k) {
-      double cs, sn;
-      nlos::cos_sin_2pi_frac(k, axes[i].m, &cs, &sn);
-      tw.push_back(make_float2((float)cs, (float)-sn));
-    }
-  }
-  if (!tw.empty()) {
-    if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&p->d_gtw, tw.size() * sizeof(float2)) != hipSuccess) {
-      delete p;
-      return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "fk_plan_create: twiddle table allocation");
-    }
-    if (hipMemcpy(p->d_gtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(p->d_gtw);
-      delete p;
-      return fail(ctx, NLOS_ERR_DEVICE, "fk_plan_create: twiddle upload failed");
-    }
-    for (int i = 0; i < 3; ++i)
-      if (*axes[i].on || (i == 0 && p->gen_xr2c)) axes[i].g->tw = p->d_gtw + off[i];
+  // general axis lengths (the x pass also for odd nt: see gen_xr2c)
+  p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
+  p->gen_y = !is_pow2_in(p->My, 8, 2048);
+  p->gen_t = !is_pow2_in(p->Mt, 8, 2048);
+  p->gen_xr2c = p->gen_x || (d->nt & 1) != 0;
+  const int m[3] = {p->Mx, p->My, p->Mt};
+  const bool use[3] = {p->gen_xr2c, p->gen_y, p->gen_t};
+  nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
+  const hipError_t e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
+                "fk_plan_create: general-length twiddle tables: %s", hipGetErrorString(e));
   }
   *out = p;
   return NLOS_OK;
@@ -748,9 +764,11 @@ nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
       d->kernel_prec > NLOS_BF16)
     return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bad precision");
   const long long p = d->pad;
-  if (!is_pow2_in(p * d->nx, 8, 2048) || !is_pow2_in(p * d->ny, 8, 2048) || !is_pow2_in(d->nt, 8, 2048))
-    return fail(nullptr, NLOS_ERR_UNSUPPORTED,
-                "rsd: pad*nx, pad*ny and nt must be powers of two in [8, 2048]");
+  for (long long m : {p * d->nx, p * d->ny, (long long)d->nt})
+    if (!is_pow2_in(m, 8, 2048) && !is_general_len(m))
+      return fail(nullptr, NLOS_ERR_UNSUPPORTED,
+                  "rsd: pad*nx, pad*ny and nt must be powers of two in [8, 2048] or even lengths in "
+                  "[8, 4096] with prime factors 2, 3, 5, 7, 11, 13");
   for (int f = 0; f < d->n_freq; ++f)
     if (d->freq_bin[f] < 1 || d->freq_bin[f] > d->nt / 2 - 1)
       return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: freq_bin[%d] = %d outside [1, nt/2 - 1]", f,
@@ -810,6 +828,7 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan* p) {
   if (p->d_chunk_wb) (void)hipFree(p->d_chunk_wb);
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_bins) (void)hipFree(p->d_bins);
+  if (p->d_gtw) (void)hipFree(p->d_gtw);
   delete p;
   return NLOS_OK;
 }
@@ -877,6 +896,14 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
   if ((e = hipMalloc(&p->d_bins, bins.size() * sizeof(int))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "bins", e);
   if ((e = hipMemcpy(p->d_bins, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(NLOS_ERR_DEVICE, "bins upload", e);
+  p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
+  p->gen_y = !is_pow2_in(p->My, 8, 2048);
+  p->gen_t = !is_pow2_in(d->nt, 8, 2048);
+  const int m[3] = {p->Mx, p->My, d->nt};
+  const bool use[3] = {p->gen_x, p->gen_y, p->gen_t};
+  nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
+  if ((e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw)) != hipSuccess)
+    return cleanup(NLOS_ERR_DEVICE, "general-length twiddle tables", e);
   *out = p;
   return NLOS_OK;
 }
@@ -905,18 +932,27 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
     ContigArgs c{};
     c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
     c.bins = p->d_bins; c.nbins = (int)Nf;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] { return nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s); }));
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] {
+      return p->gen_t ? nlos::launch_gen_contig(p->gt, false, nlos::CL_REAL, nlos::CS_BINS, c, s)
+                      : nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s);
+    }));
   }
   // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
   a.in = d_phasor ? d_phasor : P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
   a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] { return nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] {
+    return p->gen_x ? nlos::launch_gen_strided(p->gx, false, nlos::ST_C64, a, (int)ny, s)
+                    : nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s);
+  }));
   // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
   a = StridedArgs{};
   a.in = X; a.out = Ph; a.in_plane = Nf; a.in_line = Mx * Nf; a.out_plane = Nf; a.out_line = Mx * Nf;
   a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_Y, [&] { return nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_Y, [&] {
+    return p->gen_y ? nlos::launch_gen_strided(p->gy, false, nlos::ST_C64, a, (int)Mx, s)
+                    : nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s);
+  }));
   // 4. radial propagation over pixel chunks: P^ -> C[pix][d]
   nlos::RsdPropArgs r{};
   r.Ph = Ph; r.Kr = p->d_kr; r.w = p->d_w; r.C = C;
@@ -928,7 +964,10 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   a = StridedArgs{};
   a.in = C; a.out = D; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;
   a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_YI, [&] { return nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_YI, [&] {
+    return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
+                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s);
+  }));
   // 6. x-IFFT, keep x < nx, |I| / (Mx My) -> vol[y][x][d], max over depth -> img
   a = StridedArgs{};
   a.in = D; a.out = d_vol; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
@@ -936,10 +975,16 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
   if (d_field) {  // the complex field I itself
     a.out = d_field; a.img = nullptr;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64_SCALED, a, (int)ny, tw, s); }));
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] {
+      return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64_SCALED, a, (int)ny, s)
+                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64_SCALED, a, (int)ny, tw, s);
+    }));
     return NLOS_OK;
   }
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] { return nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s); }));
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] {
+    return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_ABS_IMG, a, (int)ny, s)
+                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s);
+  }));
   return NLOS_OK;
 }
 

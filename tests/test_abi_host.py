@@ -116,7 +116,16 @@ def test_rsd_validation():
     assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG       # bin 0
     bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5, 128], [1, 1], 8, 0.2, 0.01)
     assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG       # bin nt/2
-    bad = nlos.RsdDesc(30, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    # general lengths: even, prime factors up to 13, at most 4096
+    ok = nlos.RsdDesc(30, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(ok) == nlos.NLOS_OK
+    ok = nlos.RsdDesc(360, 260, 1500, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(ok) == nlos.NLOS_OK
+    bad = nlos.RsdDesc(17, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED
+    bad = nlos.RsdDesc(32, 32, 375, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
+    assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED     # odd t length
+    bad = nlos.RsdDesc(32, 32, 4100, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01)
     assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED
     bad = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 0, 0.2, 0.01)
     assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_INVALID_ARG
