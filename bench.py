@@ -8,7 +8,7 @@ complete nlos_fk call (5 kernel passes + the image clear).  Prints one JSON
 line with volumes/s, the HBM roofline of the dominant kernel and the FP64
 oracle's CPU throughput on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload fk_c4|fk_c3|fk_office|rsd_c3|rsd_c2|bin_c2]
+    python bench.py [--steps K] [--warmup W] [--workload fk_c4|fk_c3|fk_office|rsd_c3|rsd_c2|rsd_office|bin_c2]
 """
 from __future__ import annotations
 
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
-                    choices=["fk_c4", "fk_c3", "fk_c1", "fk_office", "rsd_c3", "rsd_c2", "bin_c2", "phasor_c2", "moe_c4",
+                    choices=["fk_c4", "fk_c3", "fk_c1", "fk_office", "rsd_c3", "rsd_c2", "rsd_office", "bin_c2", "phasor_c2", "moe_c4",
                              "moe_c3", "merge_c4", "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
@@ -465,6 +465,22 @@ def main():
         phasor_cmp = {"photons_to_rsd_via_phasor_binning_ms": round(clock2(via_phasors) * 1e3, 4),
                       "photons_to_rsd_via_histogram_ms": round(clock2(via_histogram) * 1e3, 4)}
 
+    # the same step as one replayed HIP graph (same buffers), against the eager launches
+    graph_cmp = None
+    if kind in ("fk", "rsd"):
+        g = plan.graph(tau, vol, img, ws)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        gsec = (time.perf_counter() - t0) / args.steps
+        g.close()
+        graph_cmp = {"eager_ms": round(sec * 1e3, 4), "graph_replay_ms": round(gsec * 1e3, 4),
+                     "speedup": round(sec / gsec, 4)}
+
     line = {
         "metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
@@ -475,6 +491,7 @@ def main():
         "serving": serving,
         "moe_vs_separate": moe_cmp,
         "phasor_vs_histogram": phasor_cmp,
+        "graph_vs_eager": graph_cmp,
         "step_frac_of_hbm": round(total_alg * value / units_per_step / (HBM_PEAK_GBS * 1e9), 4),
         "step_bytes": total_alg,
     }

@@ -53,6 +53,7 @@ typedef struct nlos_rsd_plan nlos_rsd_plan;
 typedef struct nlos_moe_plan nlos_moe_plan;
 typedef struct nlos_phasor_plan nlos_phasor_plan;
 typedef struct nlos_merge nlos_merge;
+typedef struct nlos_graph nlos_graph;
 
 /* ------------------------------------------------------------------------ */
 /* Context                                                                   */
@@ -333,6 +334,23 @@ nlos_status nlos_merge_reset(nlos_merge *merge);
  * a state must not be pushed from two streams at once. */
 nlos_status nlos_merge_push(nlos_ctx *ctx, nlos_merge *merge, const float *d_frame, float *d_merged,
                             float *d_coherence);
+
+/* Graph replay (the paper measures the launch overhead that CUDA graphs remove, Section
+ * 5): captures one nlos_fk (nlos_rsd) call with these exact buffers -- same argument
+ * meaning, layout and workspace rules, except that d_ws is required (no pool) -- into an
+ * instantiated HIP graph owned by *out; nothing runs at creation.  nlos_graph_launch
+ * replays it on the context's current stream: the same kernels on the same pointers, so
+ * results are bitwise equal to the eager call on the same inputs.  The buffers must stay
+ * allocated while the graph lives; new inputs are written into d_tau between replays
+ * (stream-ordered), and replays on one workspace must not overlap (same stream, or
+ * ordered by events).  Per-pass timing does not cover replays.  A graph belongs to the
+ * device it was created on. */
+nlos_status nlos_fk_graph_create(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_vol,
+                                 float *d_img, void *d_ws, size_t ws_bytes, nlos_graph **out);
+nlos_status nlos_rsd_graph_create(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
+                                  float *d_img, void *d_ws, size_t ws_bytes, nlos_graph **out);
+nlos_status nlos_graph_launch(nlos_ctx *ctx, const nlos_graph *graph);
+nlos_status nlos_graph_destroy(nlos_graph *graph);
 
 #ifdef __cplusplus
 }

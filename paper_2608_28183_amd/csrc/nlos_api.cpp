@@ -1048,6 +1048,108 @@ nlos_status nlos_rsd_complex(nlos_ctx* ctx, const nlos_rsd_plan* p, const float*
 }
 
 // ---------------------------------------------------------------------------
+// graph replay: one reconstruction with fixed buffers as an instantiated HIP graph
+// ---------------------------------------------------------------------------
+
+struct nlos_graph {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// Captures run(stream) on a private default-priority stream and instantiates it.  Per-pass
+// timing is suspended during the capture, so the graph holds the kernel launches only.
+extern "C++" {
+template <class Run>
+static nlos_status capture_graph(nlos_ctx* ctx, const char* who, Run run, nlos_graph** out) {
+  hipStream_t cs = nullptr;
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  nlos_status st = NLOS_OK;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = run(cs);
+    const hipError_t e_end = hipStreamEndCapture(cs, &g);
+    if (st == NLOS_OK) e = e_end;
+  }
+  ctx->timing = timing;
+  nlos_graph* gr = nullptr;
+  if (st == NLOS_OK && e == hipSuccess) {
+    gr = new (std::nothrow) nlos_graph();
+    if (!gr) {
+      st = fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "%s: host allocation", who);
+    } else {
+      gr->device = ctx->device;
+      gr->graph = g;
+      e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != NLOS_OK || e != hipSuccess) {
+    if (gr && gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    delete gr;
+    if (g) (void)hipGraphDestroy(g);
+    if (st != NLOS_OK) return st;
+    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE, "%s: graph capture: %s",
+                who, hipGetErrorString(e));
+  }
+  *out = gr;
+  return NLOS_OK;
+}
+}  // extern "C++"
+
+nlos_status nlos_fk_graph_create(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_vol,
+                                 float* d_img, void* d_ws, size_t ws_bytes, nlos_graph** out) {
+  if (!ctx || !p || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: NULL argument");
+  if (!d_tau || !d_ws) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: d_tau and d_ws are required");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: d_tau must be 8-byte aligned");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: plan of another device");
+  size_t need = 0;
+  nlos_status st = nlos_fk_workspace_bytes(&p->d, &need);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  if ((st = get_workspace(ctx, d_ws, ws_bytes, need, &ws)) != NLOS_OK) return st;
+  return capture_graph(
+      ctx, "nlos_fk_graph_create", [&](hipStream_t cs) { return fk_run(ctx, p, cs, d_tau, d_vol, d_img, ws); }, out);
+}
+
+nlos_status nlos_rsd_graph_create(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, float* d_vol,
+                                  float* d_img, void* d_ws, size_t ws_bytes, nlos_graph** out) {
+  if (!ctx || !p || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: NULL argument");
+  if (!d_tau || !d_ws) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: d_tau and d_ws are required");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: plan of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  void* ws = nullptr;
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).total * 8, &ws);
+  if (st != NLOS_OK) return st;
+  return capture_graph(
+      ctx, "nlos_rsd_graph_create", [&](hipStream_t cs) { return rsd_run(ctx, p, cs, d_tau, d_vol, d_img, ws); }, out);
+}
+
+nlos_status nlos_graph_launch(nlos_ctx* ctx, const nlos_graph* g) {
+  if (!ctx || !g) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_graph_launch: ctx or graph is NULL");
+  if (g->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_graph_launch: graph of another device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipGraphLaunch(g->exec, ctx->stream));
+  return NLOS_OK;
+}
+
+nlos_status nlos_graph_destroy(nlos_graph* g) {
+  if (!g) return NLOS_OK;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // coherence-weighted temporal merging (Section 4.4, Eq. 8-9)
 // ---------------------------------------------------------------------------
 

@@ -116,6 +116,10 @@ _SIGNATURES = {
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_VP)]),
     "nlos_moe_plan_destroy": (_ST, [_VP]),
     "nlos_moe": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_fk_graph_create": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "nlos_rsd_graph_create": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "nlos_graph_launch": (_ST, [_VP, _VP]),
+    "nlos_graph_destroy": (_ST, [_VP]),
 }
 
 _lib = None
@@ -403,6 +407,30 @@ def nlos_fk_complex(ctx: int, plan: int, tau, psi, ws=None) -> None:
 def nlos_rsd_complex(ctx: int, plan: int, tau, field, ws=None) -> None:
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().nlos_rsd_complex(ctx, plan, _ptr(tau), _ptr(field), _ptr(ws), ws_bytes), "nlos_rsd_complex", ctx)
+
+
+def nlos_fk_graph_create(ctx: int, plan: int, tau, vol, img, ws) -> int:
+    ws_bytes = ws.numel() * ws.element_size()
+    out = ctypes.c_void_p()
+    _check(lib().nlos_fk_graph_create(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes,
+                                      ctypes.byref(out)), "nlos_fk_graph_create", ctx)
+    return out.value
+
+
+def nlos_rsd_graph_create(ctx: int, plan: int, tau, vol, img, ws) -> int:
+    ws_bytes = ws.numel() * ws.element_size()
+    out = ctypes.c_void_p()
+    _check(lib().nlos_rsd_graph_create(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes,
+                                       ctypes.byref(out)), "nlos_rsd_graph_create", ctx)
+    return out.value
+
+
+def nlos_graph_launch(ctx: int, graph: int) -> None:
+    _check(lib().nlos_graph_launch(ctx, graph), "nlos_graph_launch", ctx)
+
+
+def nlos_graph_destroy(graph: int) -> None:
+    _check(lib().nlos_graph_destroy(graph), "nlos_graph_destroy")
 
 
 def nlos_merge_create(ctx: int, n_values: int, window: int, eps: float = 1e-6) -> int:

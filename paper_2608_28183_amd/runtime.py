@@ -35,6 +35,30 @@ class Context:
             pass
 
 
+class Graph:
+    """One reconstruction captured with fixed buffers (nlos_*_graph_create); replay()
+    runs it on the context's stream.  The buffers are held for the graph's lifetime:
+    write new inputs into ``tau`` and read results from ``vol`` / ``img`` between replays."""
+
+    def __init__(self, ctx: Context, handle: int, tau, vol, img, ws, plan):
+        self.ctx, self.handle = ctx, handle
+        self.tau, self.vol, self.img, self.ws, self.plan = tau, vol, img, ws, plan
+
+    def replay(self) -> None:
+        nlos.nlos_graph_launch(self.ctx.handle, self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            nlos.nlos_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class FkPlan:
     def __init__(self, ctx: Context, ny: int, nx: int, nt: int, wall_w: float, wall_h: float,
                  bin_ps: float, pad: int = 2, prec: str = "fp32"):
@@ -52,6 +76,12 @@ class FkPlan:
         assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
         nlos.nlos_fk(self.ctx.handle, self.handle, tau, vol, img, ws)
         return vol, img
+
+    def graph(self, tau: torch.Tensor, vol=None, img=None, ws=None) -> Graph:
+        """This plan's reconstruction of these buffers as a replayable graph."""
+        ws = self.workspace() if ws is None else ws
+        h = nlos.nlos_fk_graph_create(self.ctx.handle, self.handle, tau, vol, img, ws)
+        return Graph(self.ctx, h, tau, vol, img, ws, self)
 
     def __del__(self):
         try:
@@ -84,6 +114,12 @@ class RsdPlan:
         assert vol is None or vol.shape == (ny, nx, self.n_depth)
         nlos.nlos_rsd(self.ctx.handle, self.handle, tau, vol, img, ws)
         return vol, img
+
+    def graph(self, tau: torch.Tensor, vol=None, img=None, ws=None) -> Graph:
+        """This plan's reconstruction of these buffers as a replayable graph."""
+        ws = self.workspace() if ws is None else ws
+        h = nlos.nlos_rsd_graph_create(self.ctx.handle, self.handle, tau, vol, img, ws)
+        return Graph(self.ctx, h, tau, vol, img, ws, self)
 
     def __del__(self):
         try:

@@ -81,7 +81,7 @@ CONFIGS: Dict[str, Config] = {
     "c4": Config("c4", 256, 256, 512, 32.0, 1.0, 1.0, 2, "mix", (0.5, 1.5), seed=1004),
     # the office grid of Table 4 (360x260x512), 5 mm pitch on a 1.8 x 1.3 m wall, padded to
     # 720x520x1024 (factors 2, 3, 5, 13): a synthetic stand-in for the captured dataset
-    "office": Config("office", 360, 260, 512, 32.0, 1.8, 1.3, 2, "mix", (0.5, 1.5), seed=1005),
+    "office": Config("office", 360, 260, 512, 32.0, 1.8, 1.3, 2, "mix", (0.5, 1.5), n_depth=51, seed=1005),
 }
 
 
