@@ -71,16 +71,21 @@ def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
     }
 
 
-def moe_pass_bytes(ny, nx, nt, pad, nf, nd, nrho):
-    """Algorithmic bytes of the mixture-of-experts passes: the f-k passes on the unscaled
-    transient (images only, no volume), the RSD phasors from the shared half spectrum,
-    the RSD propagation and inverse passes (image only) and the mixture."""
+def moe_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, shared=False):
+    """Algorithmic bytes of the mixture-of-experts passes: the f-k passes (images only,
+    no volume), the RSD phasors -- from the shared half spectrum (shared schedule) or the
+    transient followed by the x and y passes (branches in sequence) -- the RSD
+    propagation and inverse passes (image only) and the mixture."""
     Mx, My = pad * nx, pad * ny
     fk = fk_pass_bytes(ny, nx, nt, pad)
     fk["fk_zi"] = 8 * ny * nx * nt + 4 * ny * nx
     rsd = rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho)
     out = {k: fk[k] for k in ("fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi", "fk_zi")}
-    out["moe_phasor"] = 8 * My * (Mx // 2 + 1) * nt + 8 * My * Mx * nf
+    if shared:
+        out["moe_phasor"] = 8 * My * (Mx // 2 + 1) * nt + 8 * My * Mx * nf
+    else:
+        for k in ("rsd_phasor", "rsd_x", "rsd_y"):
+            out[k] = rsd[k]
     out["rsd_propagate"] = rsd["rsd_propagate"]
     out["rsd_yi"] = rsd["rsd_yi"]
     out["rsd_xi"] = 8 * ny * Mx * nd + 4 * ny * nx
@@ -298,12 +303,12 @@ def main():
             fkp(tau, None, im2, ws2)
             rsp(tau, None, im2, ws2)
 
-        sqp = runtime.MoePlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad,
+        shp = runtime.MoePlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad,
                               p.freq_bins, p.weights, p.n_depth, p.depth0, p.depth_step,
-                              shared_spectrum=False)
+                              shared_spectrum=True)
 
-        def sequential():
-            sqp(tau, im2, None, None, ws)
+        def shared():
+            shp(tau, im2, None, None, ws)
     elif kind == "merge":
         # one frame = the complex f-k field of a transient, then coherence merging over the
         # last 3 frames (Eq. 8-9); the input alternates between two noise draws
@@ -446,9 +451,9 @@ def main():
                 fn()
             torch.cuda.synchronize()
             return (time.perf_counter() - t0) / args.steps
-        sep, sq = clock(separate), clock(sequential)
-        moe_cmp = {"moe_shared_spectrum_ms": round(sec * 1e3, 4),
-                   "moe_branches_in_sequence_ms": round(sq * 1e3, 4),
+        sep, sh = clock(separate), clock(shared)
+        moe_cmp = {"moe_branches_in_sequence_ms": round(sec * 1e3, 4),
+                   "moe_shared_spectrum_ms": round(sh * 1e3, 4),
                    "separate_fk_then_rsd_ms": round(sep * 1e3, 4), "speedup_vs_separate": round(sep / sec, 3)}
 
     phasor_cmp = None

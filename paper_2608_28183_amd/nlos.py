@@ -357,7 +357,7 @@ def nlos_moe_workspace_bytes(fk: nlos_fk_desc, rsd: "RsdDesc") -> int:
 
 
 def nlos_moe_plan_create(ctx: int, fk: nlos_fk_desc, rsd: "RsdDesc", beta: float = 0.3,
-                         eps: float = 1e-6, shared_spectrum: bool = True) -> int:
+                         eps: float = 1e-6, shared_spectrum: bool = False) -> int:
     out = ctypes.c_void_p()
     _check(lib().nlos_moe_plan_create(ctx, ctypes.byref(fk), ctypes.byref(rsd.c), beta, eps,
                                       int(bool(shared_spectrum)), ctypes.byref(out)),

@@ -135,7 +135,7 @@ class MoePlan:
                  bin_ps: float, pad: int, freq_bins, weights, n_depth: int, depth0: float,
                  depth_step: float, beta: float = 0.3, eps: float = 1e-6, sigma_s: int = 2,
                  sigma_t: int = 0, delta: float = 0.0, kernel_prec: str = "fp32",
-                 shared_spectrum: bool = True):
+                 shared_spectrum: bool = False):
         self.ctx = ctx
         self.shape = (ny, nx, nt)
         self.fk_desc = nlos.fk_desc(nx, ny, nt, wall_w, wall_h, bin_ps, pad, "fp32")
