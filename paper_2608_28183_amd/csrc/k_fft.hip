@@ -189,7 +189,7 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
       const int f = k % a.nbins;
       const long long ln = line0 + ll;
       if (ln < a.nlines)
-        static_cast<float2*>(a.out)[ln * a.nbins + f] = lds[ll * C::LSTRIDE + swz(a.bins[f])];
+        static_cast<float2*>(a.out)[ln * a.out_line + f] = lds[ll * C::LSTRIDE + swz(a.bins[f])];
     }
   } else if constexpr (ST == CS_ABS2_MAX) {
     // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]

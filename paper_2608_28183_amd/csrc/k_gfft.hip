@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kGenMaxThreads) void gen_contig(ContigArgs a, GenPl
     for (int k = tid; k < L * a.nbins; k += blockDim.x) {
       const int ll = k / a.nbins, f = k % a.nbins;
       if (line0 + ll < a.nlines)
-        static_cast<float2*>(a.out)[(line0 + ll) * a.nbins + f] = glds[ll * n + a.bins[f]];
+        static_cast<float2*>(a.out)[(line0 + ll) * a.out_line + f] = glds[ll * n + a.bins[f]];
     }
   } else if constexpr (ST == CS_ABS2_MAX) {
     float m = 0.f;

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
     // unused slots have wa = wb = 0 and read pixel 0's row
     const float wa = a.chunk_wa[g * kGroupPix + lane];
     const float wb = a.chunk_wb[g * kGroupPix + lane];
-    const float2* __restrict__ ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * Nf;
+    const float2* __restrict__ ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
     long long o0 = (long long)i0 * Nf * Nd + d0;
     long long o1 = (long long)i1 * Nf * Nd + d0;
     if (d0 + kDepths <= Nd) {
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
     }
   }
   if (pix < 0) return;
-  float2* out = a.C + (long long)pix * Nd + d0;
+  float2* out = a.C + (long long)pix * a.c_stride + d0;
 #pragma unroll
   for (int j = 0; j < kDepths; ++j)
     if (d0 + j < Nd) out[j] = acc[j];

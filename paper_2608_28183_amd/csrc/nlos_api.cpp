@@ -720,12 +720,18 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
 //   E: y-FFT output P^ [My][Mx][Nf]
 struct RsdLayout {
   size_t b_off, e_off, total;
+  size_t nfs, nds;  // row strides (elements) of the frequency and depth contiguous arrays
 };
+// Rows of Nf frequencies or Nd depths are padded to a multiple of 16 complex values (128
+// bytes), so that the column tiles of the strided passes cover whole cache lines.
 static RsdLayout rsd_layout(const nlos_rsd_desc* d) {
   const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny;
-  const size_t nf = d->n_freq, nd = d->n_depth, ny = d->ny, nx = d->nx;
   auto up = [](size_t n) { return (n + 31) / 32 * 32; };
+  auto up16 = [](size_t n) { return (n + 15) / 16 * 16; };
+  const size_t nf = up16(d->n_freq), nd = up16(d->n_depth), ny = d->ny, nx = d->nx;
   RsdLayout L;
+  L.nfs = nf;
+  L.nds = nd;
   const size_t a = up(std::max(ny * nx * nf, ny * Mx * nd));
   const size_t b = up(std::max(ny * Mx * nf, My * Mx * nd));
   L.b_off = a;
@@ -916,11 +922,13 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   const long long Nf = d.n_freq, Nd = d.n_depth;
   const RsdLayout L = rsd_layout(&d);
   float2* base = static_cast<float2*>(ws);
-  float2* P = base;                 // [ny][nx][Nf]
-  float2* X = base + L.b_off;       // [ny][Mx][Nf]
-  float2* Ph = base + L.e_off;      // [My][Mx][Nf]
-  float2* C = base + L.b_off;       // [My][Mx][Nd]
-  float2* D = base;                 // [ny][Mx][Nd]
+  // frequency rows hold Nf values in a stride of Nfs, depth rows Nd in Nds
+  const long long Nfs = (long long)L.nfs, Nds = (long long)L.nds;
+  float2* P = base;                 // [ny][nx][Nfs]
+  float2* X = base + L.b_off;       // [ny][Mx][Nfs]
+  float2* Ph = base + L.e_off;      // [My][Mx][Nfs]
+  float2* C = base + L.b_off;       // [My][Mx][Nds]
+  float2* D = base;                 // [ny][Mx][Nds]
   const float2* tw = ctx->d_tw;
   if (d_img)
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
@@ -930,8 +938,8 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   // 1. phasors: t-FFT of each pixel, bins k_f -> P[y][x][f] (or the caller's phasors)
   if (!d_phasor) {
     ContigArgs c{};
-    c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.n_in = (int)nt; c.n_out = (int)nt;
-    c.bins = p->d_bins; c.nbins = (int)Nf;
+    c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.out_line = Nfs; c.n_in = (int)nt;
+    c.n_out = (int)nt; c.bins = p->d_bins; c.nbins = (int)Nf;
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] {
       return p->gen_t ? nlos::launch_gen_contig(p->gt, false, nlos::CL_REAL, nlos::CS_BINS, c, s)
                       : nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s);
@@ -939,15 +947,16 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   }
   // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
-  a.in = d_phasor ? d_phasor : P; a.out = X; a.in_plane = nx * Nf; a.in_line = Nf; a.out_plane = Mx * Nf; a.out_line = Nf;
-  a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
+  const long long Pin = d_phasor ? Nf : Nfs;  // the caller's phasors are [ny][nx][Nf]
+  a.in = d_phasor ? d_phasor : P; a.out = X; a.in_plane = nx * Pin; a.in_line = Pin; a.out_plane = Mx * Nfs;
+  a.out_line = Nfs; a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] {
     return p->gen_x ? nlos::launch_gen_strided(p->gx, false, nlos::ST_C64, a, (int)ny, s)
                     : nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s);
   }));
   // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
   a = StridedArgs{};
-  a.in = X; a.out = Ph; a.in_plane = Nf; a.in_line = Mx * Nf; a.out_plane = Nf; a.out_line = Mx * Nf;
+  a.in = X; a.out = Ph; a.in_plane = Nfs; a.in_line = Mx * Nfs; a.out_plane = Nfs; a.out_line = Mx * Nfs;
   a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_Y, [&] {
     return p->gen_y ? nlos::launch_gen_strided(p->gy, false, nlos::ST_C64, a, (int)Mx, s)
@@ -958,11 +967,12 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   r.Ph = Ph; r.Kr = p->d_kr; r.w = p->d_w; r.C = C;
   r.chunk_i0 = p->d_chunk_i0; r.chunk_pix = p->d_chunk_pix; r.chunk_wa = p->d_chunk_wa;
   r.chunk_wb = p->d_chunk_wb; r.nchunks = p->nchunks;
-  r.Nf = (int)Nf; r.Nd = (int)Nd; r.cut_idx = p->g.cut_idx; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
+  r.Nf = (int)Nf; r.Nd = (int)Nd; r.ph_stride = (int)Nfs; r.c_stride = (int)Nds;
+  r.cut_idx = p->g.cut_idx; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
   // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d]
   a = StridedArgs{};
-  a.in = C; a.out = D; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;
+  a.in = C; a.out = D; a.in_plane = Nds; a.in_line = Mx * Nds; a.out_plane = Nds; a.out_line = Mx * Nds;
   a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_YI, [&] {
     return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
@@ -970,7 +980,7 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   }));
   // 6. x-IFFT, keep x < nx, |I| / (Mx My) -> vol[y][x][d], max over depth -> img
   a = StridedArgs{};
-  a.in = D; a.out = d_vol; a.in_plane = Mx * Nd; a.in_line = Nd; a.out_plane = nx * Nd; a.out_line = Nd;
+  a.in = D; a.out = d_vol; a.in_plane = Mx * Nds; a.in_line = Nds; a.out_plane = nx * Nd; a.out_line = Nd;
   a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
   if (d_field) {  // the complex field I itself
@@ -1381,7 +1391,8 @@ nlos_status nlos_moe(nlos_ctx* ctx, const nlos_moe_plan* p, const float* d_tau, 
   r.Ph = Ph; r.Kr = p->rsd->d_kr; r.w = p->rsd->d_w; r.C = Cr;
   r.chunk_i0 = p->rsd->d_chunk_i0; r.chunk_pix = p->rsd->d_chunk_pix; r.chunk_wa = p->rsd->d_chunk_wa;
   r.chunk_wb = p->rsd->d_chunk_wb; r.nchunks = p->rsd->nchunks;
-  r.Nf = (int)Nf; r.Nd = (int)Nd; r.cut_idx = p->rsd->g.cut_idx; r.kernel_fp16 = rd.kernel_prec == NLOS_FP16;
+  r.Nf = (int)Nf; r.Nd = (int)Nd; r.ph_stride = (int)Nf; r.c_stride = (int)Nd;
+  r.cut_idx = p->rsd->g.cut_idx; r.kernel_fp16 = rd.kernel_prec == NLOS_FP16;
   HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s1); }));
   a = StridedArgs{};
   a.in = Cr; a.out = Dr; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;

@@ -47,7 +47,7 @@ struct ContigArgs {
   float* img;          // CS_ABS_IMG: img[(ln % img_lines) * out_line + n] = max over lines;
                        // CS_ABS2_MAX: img[ln] = max over the line
   long long img_lines;
-  const int* bins;     // CS_BINS: out[ln * nbins + f] = X[bins[f]]
+  const int* bins;     // CS_BINS: out[ln * out_line + f] = X[bins[f]], f < nbins
   int nbins;
   const int* e_in;     // FP16 input: holds value * 2^(*e_in)
 };
@@ -102,6 +102,7 @@ struct RsdPropArgs {
   const float* chunk_wb;   // [nchunks][64] a alpha, 0 in unused slots
   long long nchunks;
   int Nf, Nd;
+  int ph_stride, c_stride;  // elements between the pixel rows of Ph and of C
   int cut_idx;
   int kernel_fp16;
 };
