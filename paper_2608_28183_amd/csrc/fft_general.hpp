@@ -2,7 +2,7 @@
 //
 // Lengths n whose prime factors are 2, 3, 5, 7, 11 and 13 (the office-scene grids of
 // the paper's Table 4 pad to 720 x 520 and to time axes of 750, 1500 or 3000 samples)
-// run as Stockham stages over radices from {2, 3, 4, 5, 7, 8, 11, 13}, chosen on the
+// run as Stockham stages over radices from {2, 3, 4, 5, 7, 8, 9, 11, 13, 16}, chosen on the
 // host (GenPlan).  A line lives in LDS for the whole transform; each stage reads all of
 // its butterfly inputs into registers, waits for the block, and writes the outputs back
 // in place, so no second buffer is needed.  Butterfly j of a stage with radix R and span
@@ -58,9 +58,39 @@ __device__ __forceinline__ void dft_prime(float2* v) {
 }
 
 template <int R, bool INV>
+__device__ __forceinline__ void dft_any(float2* v);
+
+// Four-step split R = N1 N2 (n = r + N1 j, k = s + N2 q): N1 DFTs of length N2 over j,
+// twiddles W_R^{r s}, N2 DFTs of length N1 over r.
+template <int R, int N1, bool INV>
+__device__ __forceinline__ void dft_split(float2* v) {
+  constexpr int N2 = R / N1;
+  float2 t[R];
+  static_for<N1>([&](auto r_) {
+    constexpr int r = decltype(r_)::value;
+    float2 u[N2];
+    static_for<N2>([&](auto j_) { u[decltype(j_)::value] = v[r + N1 * decltype(j_)::value]; });
+    dft_any<N2, INV>(u);
+    static_for<N2>([&](auto s_) {
+      constexpr int s = decltype(s_)::value;
+      t[r * N2 + s] = twc<R, r * s, INV>(u[s]);
+    });
+  });
+  static_for<N2>([&](auto s_) {
+    constexpr int s = decltype(s_)::value;
+    float2 u[N1];
+    static_for<N1>([&](auto r_) { u[decltype(r_)::value] = t[decltype(r_)::value * N2 + s]; });
+    dft_any<N1, INV>(u);
+    static_for<N1>([&](auto q_) { v[s + N2 * decltype(q_)::value] = u[decltype(q_)::value]; });
+  });
+}
+
+template <int R, bool INV>
 __device__ __forceinline__ void dft_any(float2* v) {
   if constexpr (R == 3 || R == 5 || R == 7 || R == 11 || R == 13) {
     dft_prime<R, INV>(v);
+  } else if constexpr (R == 9) {
+    dft_split<9, 3, INV>(v);
   } else {
     dft<R, INV>(v);
   }
@@ -144,6 +174,8 @@ __device__ __forceinline__ void gen_fft(float2* line, int ls, const GenPlan& g, 
       case 5: gen_stage<5, cdiv(EMAX, 5), INV>(base, ls, g.n, ns, p, P, tw); break;
       case 7: gen_stage<7, cdiv(EMAX, 7), INV>(base, ls, g.n, ns, p, P, tw); break;
       case 8: gen_stage<8, cdiv(EMAX, 8), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 9: gen_stage<9, cdiv(EMAX, 9), INV>(base, ls, g.n, ns, p, P, tw); break;
+      case 16: gen_stage<16, cdiv(EMAX, 16), INV>(base, ls, g.n, ns, p, P, tw); break;
       case 11: gen_stage<11, cdiv(EMAX, 11), INV>(base, ls, g.n, ns, p, P, tw); break;
       case 13: gen_stage<13, cdiv(EMAX, 13), INV>(base, ls, g.n, ns, p, P, tw); break;
       default: break;  // the host plans only the radices above

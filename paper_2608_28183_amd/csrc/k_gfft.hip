@@ -224,10 +224,14 @@ bool gen_plan_radices(int n, GenPlan* g) {
   int e = 0;
   while (m % 2 == 0) { m /= 2; ++e; }
   int rad[kGenMaxStages + 8];
-  while (e > 0) {  // the power-of-two part in radices 8, 4, 2
-    const int r = e >= 3 ? 8 : e == 2 ? 4 : 2;
+  while (e > 0) {  // the power-of-two part in radices 16, 8, 4, 2 (2^5 as 8 x 4)
+    const int r = (e >= 4 && e != 5) ? 16 : e >= 3 ? 8 : e == 2 ? 4 : 2;
     rad[k++] = r;
     e -= ilog2i(r);
+  }
+  while (m % 9 == 0) {  // pairs of 3 as radix 9
+    m /= 9;
+    rad[k++] = 9;
   }
   for (int pr : {3, 5, 7, 11, 13})
     while (m % pr == 0) {

@@ -714,10 +714,11 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
 // RSD
 // ---------------------------------------------------------------------------
 
-// RSD workspace (complex elements), frequency / depth contiguous:
-//   A: phasors P [ny][nx][Nf], later the y-IFFT output D [ny][Mx][Nd]
-//   B: x-FFT output [ny][Mx][Nf], later the propagated spectra C [My][Mx][Nd]
-//   E: y-FFT output P^ [My][Mx][Nf]
+// RSD workspace (complex elements), frequency / depth contiguous, rows of Nf (Nd) values
+// at a stride of Nfs (Nds), rounded up to 16:
+//   A: phasors P [ny][nx][Nfs], later the y-IFFT output D [ny][Mx][Nds]
+//   B: x-FFT output [ny][Mx][Nfs], later the propagated spectra C [My][Mx][Nds]
+//   E: y-FFT output P^ [My][Mx][Nfs]
 struct RsdLayout {
   size_t b_off, e_off, total;
   size_t nfs, nds;  // row strides (elements) of the frequency and depth contiguous arrays
