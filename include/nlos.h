@@ -336,8 +336,9 @@ nlos_status nlos_merge_reset(nlos_merge *merge);
 nlos_status nlos_merge_push(nlos_ctx *ctx, nlos_merge *merge, const float *d_frame, float *d_merged,
                             float *d_coherence);
 
-/* Graph replay (the paper measures the launch overhead that CUDA graphs remove, Section
- * 5): captures one nlos_fk (nlos_rsd) call with these exact buffers -- same argument
+/* Graph replay (the paper records each frame's launch sequence into a graph and replays
+ * it, Section 2.2, and measures the gain in its ablations, Section 5.2): captures one
+ * nlos_fk (nlos_rsd) call with these exact buffers -- same argument
  * meaning, layout and workspace rules, except that d_ws is required (no pool) -- into an
  * instantiated HIP graph owned by *out; nothing runs at creation.  nlos_graph_launch
  * replays it on the context's current stream: the same kernels on the same pointers, so
