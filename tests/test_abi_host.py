@@ -196,6 +196,12 @@ def test_moe_validation_and_workspace():
     assert nlos.nlos_moe_check(fd3, rd) == nlos.NLOS_ERR_INVALID_ARG
     fd4 = nlos.fk_desc(cfg.nx, cfg.ny, cfg.nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, pad=2, prec="fp16")
     assert nlos.nlos_moe_check(fd4, rd) == nlos.NLOS_ERR_UNSUPPORTED
+    # the mixture runs on power-of-two grids only
+    cm = scenes.small_config(30, 26, 120, bin_ps=48)
+    rdm, _ = _rsd_desc(cm)
+    fdm = nlos.fk_desc(cm.nx, cm.ny, cm.nt, cm.wall_w, cm.wall_h, cm.bin_ps, pad=2)
+    assert nlos.nlos_fk_check(fdm) == nlos.NLOS_OK and nlos.nlos_rsd_check(rdm) == nlos.NLOS_OK
+    assert nlos.nlos_moe_check(fdm, rdm) == nlos.NLOS_ERR_UNSUPPORTED
     assert nlos.nlos_moe_check(fd, rd, beta=-0.1) == nlos.NLOS_ERR_INVALID_ARG
     assert nlos.nlos_moe_check(fd, rd, eps=0.0) == nlos.NLOS_ERR_INVALID_ARG
     up = lambda b: (b + 255) // 256 * 256  # noqa: E731
