@@ -34,8 +34,10 @@ SHAPES = [
     (520, 8, 8, 1),     # 520-point y lines
     (507, 4, 4, 2),     # 1014-point y lines (2 x 3 x 13 x 13)
     (4, 1155, 4, 2),    # 2310-point x lines (2 x 3 x 5 x 7 x 11)
-    (4, 4, 1500, 2),    # 3000-point t columns (the longest general column)
+    (4, 4, 1500, 2),    # 3000-point t columns (2^3 x 3 x 5^3)
     (52, 72, 128, 2),   # the office grid at a fifth of its size
+    (4, 2048, 4, 2),    # the longest general line, 4096 points along x (one-column tiles)
+    (4, 4, 2048, 2),    # 4096-point t columns and z lines
 ]
 
 
