@@ -479,16 +479,18 @@ hipError_t launch_fk_xr2c(int n, const FkXArgs& a, int ny, const float2* tw, hip
 }
 
 // column pass: 16 samples per thread (64 threads per column) from timing sweeps at
-// 1024-point columns; persistent blocks, 16 per CU (4096 measured 1-3 % faster than 2048
-// at 256x256x512 in every precision, 1024 slower)
-constexpr long long kColumnBlocks = 4096;
+// 1024-point columns; persistent blocks: 4096 for columns up to 1024 points (1-3 % faster
+// than 2048 at 256x256x512 in every precision, 1024 slower), 2048 for 2048-point columns
+// (4 % faster than 4096 at 128x128x1024)
+constexpr long long column_blocks(int n) { return n >= 2048 ? 2048 : 4096; }
 
 template <int N, int SP>
 static hipError_t launch_pair_n(const FkPairArgs& a, const float2* tw, hipStream_t s) {
   constexpr int E = (N >= 1024) ? 16 : default_e(N);
   using C = ContigCfg<N, E>;
   const long long groups = (a.nwork + C::L - 1) / C::L;
-  dim3 grid((unsigned)(groups < kColumnBlocks ? groups : kColumnBlocks));
+  constexpr long long B = column_blocks(N);
+  dim3 grid((unsigned)(groups < B ? groups : B));
   // padded volume, four-byte storage (FP32 keeps its guarded loads: the folded form
   // raised its registers from 157 to 173 and its occupancy from 3 to 2)
   const bool half = SP != SP_F32 && 2 * a.nt == N;
