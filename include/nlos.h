@@ -182,9 +182,13 @@ typedef struct {
                             requires a finite B */
 } nlos_fk_desc;
 
-/* Host-only validation: dims >= 1, nt >= 2, pad in {1, 2}, pad*nx, pad*ny and
- * pad*nt powers of two in [8, 2048] (else NLOS_ERR_UNSUPPORTED), positive
- * finite geometry. */
+/* Host-only validation: dims >= 1, nt >= 2, pad in {1, 2}, positive finite geometry;
+ * each of pad*nx, pad*ny and pad*nt either a power of two in [8, 2048] or an even
+ * length in [8, 4096] whose prime factors are 2, 3, 5, 7, 11 and 13 (the grids of the
+ * paper's Table 4, e.g. 360 x 260 x 512 padded to 720 x 520 x 1024), else
+ * NLOS_ERR_UNSUPPORTED.  Grids with any such general length run on FP32 storage only
+ * (NLOS_FP16 / NLOS_BF16 there: NLOS_ERR_UNSUPPORTED); results meet the same FP32
+ * accuracy as power-of-two grids. */
 nlos_status nlos_fk_check(const nlos_fk_desc *desc);
 /* Exact device workspace one nlos_fk call needs (host only): about half the FP32
  * figure for NLOS_FP16 / NLOS_BF16 (FP16 adds 4.3 KB of scale scratch). */
@@ -238,9 +242,10 @@ typedef struct {
   int n_r_min, n_r, n_rho_min, n_rho, cut_idx, last_base;
 } nlos_rsd_geometry;
 
-/* Host-only validation: dims >= 1, pad in {1, 2}, pad*nx, pad*ny and nt powers
- * of two in [8, 2048] (else NLOS_ERR_UNSUPPORTED), frequency bins in range,
- * positive spacings, n_depth in [1, 4096], sigma_s in {1, 2}. */
+/* Host-only validation: dims >= 1, pad in {1, 2}; pad*nx, pad*ny and nt each a power
+ * of two in [8, 2048] or an even length in [8, 4096] with prime factors 2, 3, 5, 7, 11,
+ * 13 (else NLOS_ERR_UNSUPPORTED); frequency bins in range, positive spacings, n_depth
+ * in [1, 4096], sigma_s in {1, 2}. */
 nlos_status nlos_rsd_check(const nlos_rsd_desc *desc);
 /* Host-only: the radial sampling geometry of desc. */
 nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc *desc, nlos_rsd_geometry *out);
@@ -277,7 +282,8 @@ nlos_status nlos_rsd_from_phasors(nlos_ctx *ctx, const nlos_rsd_plan *plan, cons
 
 /* Host-only validation: both descriptors valid, describing the same transient and grid
  * (nx, ny, nt, pad, bin_ps equal; dx_m = wall_w_m / nx, dy_m = wall_h_m / ny to 1e-9
- * relative), FP32 intermediates (kernel_prec may be FP16), beta >= 0, eps > 0. */
+ * relative), FP32 intermediates (kernel_prec may be FP16), power-of-two padded sizes
+ * (else NLOS_ERR_UNSUPPORTED), beta >= 0, eps > 0. */
 nlos_status nlos_moe_check(const nlos_fk_desc *fk, const nlos_rsd_desc *rsd, double beta, double eps);
 /* Exact device workspace of one nlos_moe call: the f-k and RSD workspaces plus two
  * images (host only). */
