@@ -26,23 +26,32 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 F32_VALU_PEAK_TFLOPS = 157.3
 
 
-def fk_pass_bytes(ny, nx, nt, pad, c=8):
+def fk_pass_bytes(ny, nx, nt, pad, c=8, xfirst=None):
     """Algorithmic HBM bytes of each f-k pass of the schedule: every pruned intermediate
     written once and read once as c-byte complex values (8: FP32; 4: FP16 / BF16) -- half spectra
     kx <= Mx/2 up to the column pass, the z-IFFT last on the cropped ny x nx columns --
-    tau read and vol written as float32."""
+    tau read and vol written as float32.  The FP32 schedule (xfirst, the default for c = 8)
+    runs the x-IFFT before the y-IFFT; the four-byte forms and the shared-spectrum mixture
+    run the y-IFFT first."""
     Mx, My = pad * nx, pad * ny
     Mh = Mx // 2 + 1
     nwork = (Mx // 2 - 1) * My + 2 * (My // 2 + 1)
-    return {
+    if xfirst is None:
+        xfirst = c == 8
+    out = {
         "fk_x": 4 * ny * nx * nt + c * ny * Mh * nt,
         "fk_y": c * ny * Mh * nt + c * My * Mh * nt,
         "fk_column": c * nwork * nt + c * My * Mx * nt,
-        "fk_yi": c * My * Mx * nt + c * ny * Mx * nt,
-        "fk_xi": c * ny * Mx * nt + c * ny * nx * nt,
         "fk_zi": c * ny * nx * nt + 4 * ny * nx * nt + 4 * ny * nx,
         "fill": 4 * ny * nx,
     }
+    if xfirst:
+        out["fk_xi"] = c * My * Mx * nt + c * My * nx * nt
+        out["fk_yi"] = c * My * nx * nt + c * ny * nx * nt
+    else:
+        out["fk_yi"] = c * My * Mx * nt + c * ny * Mx * nt
+        out["fk_xi"] = c * ny * Mx * nt + c * ny * nx * nt
+    return out
 
 
 def fk_full_schedule_bytes(ny, nx, nt, pad):
@@ -77,7 +86,7 @@ def moe_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, shared=False):
     transient followed by the x and y passes (branches in sequence) -- the RSD
     propagation and inverse passes (image only) and the mixture."""
     Mx, My = pad * nx, pad * ny
-    fk = fk_pass_bytes(ny, nx, nt, pad)
+    fk = fk_pass_bytes(ny, nx, nt, pad, xfirst=not shared)
     fk["fk_zi"] = 8 * ny * nx * nt + 4 * ny * nx
     rsd = rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho)
     out = {k: fk[k] for k in ("fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi", "fk_zi")}

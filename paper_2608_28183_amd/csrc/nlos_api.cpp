@@ -105,7 +105,10 @@ FkLayout fk_layout(const nlos_fk_desc* d) {
   L.rs_half = fk_row_stride(Mx / 2 + 1, nt, L.es);
   L.rs_full = fk_row_stride(Mx, nt, L.es);
   L.w2_off = ny * L.rs_half;
-  const size_t a = std::max((ny + My) * L.rs_half, ny * L.rs_full);
+  // region A also holds the FP32 schedule's [My][nx][nt] x-IFFT output (never the
+  // largest tenant for pad 1 or 2, but bounded here all the same)
+  const size_t a = std::max({(ny + My) * L.rs_half, ny * L.rs_full,
+                             My * fk_row_stride((size_t)d->nx, nt, L.es)});
   const size_t align = 256 / L.es;
   L.b_off = (a + align - 1) / align * align;
   L.total = L.b_off + My * L.rs_full;
@@ -650,26 +653,51 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] {
     return p->gen_t ? nlos::launch_gen_column_pair(p->gt, c, s) : nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp);
   }));
-  // pass 4: y-IFFT, keep y < ny
-  a = StridedArgs{};
-  a.in = W3; a.out = W4;
-  a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
-  a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-  a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
-    return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
-                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true);
-  }));
-  // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
-  a = StridedArgs{};
-  a.in = W4; a.out = W5;
-  a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
-  a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-  a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
-  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
-    return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)ny, s)
-                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true);
-  }));
+  if (sp == nlos::SP_F32) {
+    // FP32 takes the x-IFFT first: it walks W3's rows 4 KB apart, which runs faster than
+    // the y-IFFT's 2 MB strides on the larger of the two inverse volumes (same bytes)
+    const long long RX = (long long)fk_row_stride((size_t)nx, (size_t)nt, L.es);
+    // pass 4: x-IFFT of W3, keep x < nx -> W4 [My][nx][nt] (row stride RX; region A holds
+    // My * RX, which is below both of its earlier tenants for pad 1 and 2)
+    a = StridedArgs{};
+    a.in = W3; a.out = W4;
+    a.in_plane = RF; a.in_line = nt; a.out_plane = RX; a.out_line = nt;
+    a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
+      return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)My, s)
+                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)My, tw, s, sp, true);
+    }));
+    // pass 5: y-IFFT, keep y < ny -> W5 [ny][nx][nt]
+    a = StridedArgs{};
+    a.in = W4; a.out = W5;
+    a.in_plane = nt; a.in_line = RX; a.out_plane = nt; a.out_line = nx * nt;
+    a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
+      return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)nx, s)
+                      : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)nx, tw, s, sp, true);
+    }));
+  } else {
+    // pass 4: y-IFFT, keep y < ny
+    a = StridedArgs{};
+    a.in = W3; a.out = W4;
+    a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
+    a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
+    a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
+      return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
+                      : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true);
+    }));
+    // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
+    a = StridedArgs{};
+    a.in = W4; a.out = W5;
+    a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
+    a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
+    a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
+      return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)ny, s)
+                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true);
+    }));
+  }
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
