@@ -26,18 +26,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 F32_VALU_PEAK_TFLOPS = 157.3
 
 
-def fk_pass_bytes(ny, nx, nt, pad, c=8, xfirst=None):
+def fk_pass_bytes(ny, nx, nt, pad, c=8, xfirst=True):
     """Algorithmic HBM bytes of each f-k pass of the schedule: every pruned intermediate
     written once and read once as c-byte complex values (8: FP32; 4: FP16 / BF16) -- half spectra
     kx <= Mx/2 up to the column pass, the z-IFFT last on the cropped ny x nx columns --
-    tau read and vol written as float32.  The FP32 schedule (xfirst, the default for c = 8)
-    runs the x-IFFT before the y-IFFT; the four-byte forms and the shared-spectrum mixture
-    run the y-IFFT first."""
+    tau read and vol written as float32.  The schedule (xfirst) runs the x-IFFT before the
+    y-IFFT; the shared-spectrum mixture runs the y-IFFT first."""
     Mx, My = pad * nx, pad * ny
     Mh = Mx // 2 + 1
     nwork = (Mx // 2 - 1) * My + 2 * (My // 2 + 1)
-    if xfirst is None:
-        xfirst = c == 8
     out = {
         "fk_x": 4 * ny * nx * nt + c * ny * Mh * nt,
         "fk_y": c * ny * Mh * nt + c * My * Mh * nt,

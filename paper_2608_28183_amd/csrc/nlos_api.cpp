@@ -90,7 +90,8 @@ size_t fk_elem_bytes(nlos_precision p) { return p == NLOS_FP32 ? 8 : 4; }
 int fk_sp(nlos_precision p) { return p == NLOS_FP16 ? nlos::SP_F16 : p == NLOS_BF16 ? nlos::SP_BF16 : nlos::SP_F32; }
 
 // f-k workspace (complex elements of es bytes): region A holds W1 [ny][Mx/2+1][nt] and
-// W2 [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [ny][Mx][nt] (rs_full);
+// W2 [My][Mx/2+1][nt] (half spectra, row stride rs_half), later W4 [My][nx][nt] (row
+// stride nx nt + 256 bytes);
 // region B holds W3 [My][Mx][nt] (rs_full), later W5 [ny][nx][nt].  FP16 appends the
 // scale scratch: kScaleBlocks partial sums and the four storage exponents.
 struct FkLayout {
@@ -105,8 +106,8 @@ FkLayout fk_layout(const nlos_fk_desc* d) {
   L.rs_half = fk_row_stride(Mx / 2 + 1, nt, L.es);
   L.rs_full = fk_row_stride(Mx, nt, L.es);
   L.w2_off = ny * L.rs_half;
-  // region A also holds the FP32 schedule's [My][nx][nt] x-IFFT output (never the
-  // largest tenant for pad 1 or 2, but bounded here all the same)
+  // region A also holds the [My][nx][nt] x-IFFT output W4 (never the largest tenant for
+  // pad 1 or 2, but bounded here all the same)
   const size_t a = std::max({(ny + My) * L.rs_half, ny * L.rs_full,
                              My * fk_row_stride((size_t)d->nx, nt, L.es)});
   const size_t align = 256 / L.es;
@@ -601,7 +602,7 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   void* W1 = base;                          // [ny][Mx/2+1][nt] half spectrum after the x pass
   void* W2 = base + L.w2_off * L.es;        // [My][Mx/2+1][nt] half spectrum after the y pass
   void* W3 = base + L.b_off * L.es;         // [My][Mx][nt] after the column pass
-  void* W4 = base;                          // [ny][Mx][nt] after the y-IFFT (W1, W2 are dead)
+  void* W4 = base;                          // [My][nx][nt] after the x-IFFT (W1, W2 are dead)
   void* W5 = W3;                            // [ny][nx][nt] after the x-IFFT (W3 is dead)
   // FP16 storage exponents: [0] W1 and W2, [1] W3, [2] W4, [3] W5
   int* ex = nullptr;
@@ -619,9 +620,10 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
 
   if (ex) {
     // FP16: power-of-two storage scales from the bound sum |tau| t/(nt-1)
+    // W4 follows the x-IFFT (its bound gains Mx), W5 the y-IFFT as well
     const int l_my = ilog2((int)My), l_mx = ilog2((int)Mx), l_norm = l_my + l_mx + ilog2(p->Mt);
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_SCALE, [&] {
-      return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, l_my, l_mx, s);
+      return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, l_mx, l_my, s);
     }));
   }
   // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx, kx in [0, Mx/2]
@@ -653,51 +655,29 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] {
     return p->gen_t ? nlos::launch_gen_column_pair(p->gt, c, s) : nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp);
   }));
-  if (sp == nlos::SP_F32) {
-    // FP32 takes the x-IFFT first: it walks W3's rows 4 KB apart, which runs faster than
-    // the y-IFFT's 2 MB strides on the larger of the two inverse volumes (same bytes)
-    const long long RX = (long long)fk_row_stride((size_t)nx, (size_t)nt, L.es);
-    // pass 4: x-IFFT of W3, keep x < nx -> W4 [My][nx][nt] (row stride RX; region A holds
-    // My * RX, which is below both of its earlier tenants for pad 1 and 2)
-    a = StridedArgs{};
-    a.in = W3; a.out = W4;
-    a.in_plane = RF; a.in_line = nt; a.out_plane = RX; a.out_line = nt;
-    a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
-      return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)My, s)
-                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)My, tw, s, sp, true);
-    }));
-    // pass 5: y-IFFT, keep y < ny -> W5 [ny][nx][nt]
-    a = StridedArgs{};
-    a.in = W4; a.out = W5;
-    a.in_plane = nt; a.in_line = RX; a.out_plane = nt; a.out_line = nx * nt;
-    a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
-      return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)nx, s)
-                      : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)nx, tw, s, sp, true);
-    }));
-  } else {
-    // pass 4: y-IFFT, keep y < ny
-    a = StridedArgs{};
-    a.in = W3; a.out = W4;
-    a.in_plane = nt; a.in_line = RF; a.out_plane = nt; a.out_line = RF;
-    a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
-    a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
-      return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
-                      : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp, true);
-    }));
-    // pass 5: x-IFFT, keep x < nx -> W5 [ny][nx][nt]
-    a = StridedArgs{};
-    a.in = W4; a.out = W5;
-    a.in_plane = RF; a.in_line = nt; a.out_plane = nx * nt; a.out_line = nt;
-    a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
-    a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
-    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
-      return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)ny, s)
-                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp, true);
-    }));
-  }
+  // The x-IFFT runs first: it walks W3's rows 4 KB apart, which runs faster than the
+  // y-IFFT's 2 MB strides on the larger of the two inverse volumes (same bytes)
+  const long long RX = (long long)fk_row_stride((size_t)nx, (size_t)nt, L.es);
+  // pass 4: x-IFFT of W3, keep x < nx -> W4 [My][nx][nt] (row stride RX)
+  a = StridedArgs{};
+  a.in = W3; a.out = W4;
+  a.in_plane = RF; a.in_line = nt; a.out_plane = RX; a.out_line = nt;
+  a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
+  a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
+    return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)My, s)
+                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)My, tw, s, sp, true);
+  }));
+  // pass 5: y-IFFT, keep y < ny -> W5 [ny][nx][nt]
+  a = StridedArgs{};
+  a.in = W4; a.out = W5;
+  a.in_plane = nt; a.in_line = RX; a.out_plane = nt; a.out_line = nx * nt;
+  a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
+  a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
+  HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
+    return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)nx, s)
+                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)nx, tw, s, sp, true);
+  }));
   // pass 6: z-IFFT of each (y, x) line (kz < nt stored, zero padded to Mt), keep z < nt,
   // |Psi|^2 and the max over depth
   ContigArgs z{};
