@@ -84,8 +84,8 @@ typedef enum {
   NLOS_PASS_FK_X = 2,          /* f-k pass 1: x-FFT with time scaling and zero padding */
   NLOS_PASS_FK_Y = 3,          /* f-k pass 2: y-FFT */
   NLOS_PASS_FK_COLUMN = 4,     /* f-k pass 3: t-FFT and Stolt remap per column */
-  NLOS_PASS_FK_YI = 5,         /* f-k pass 4: y-IFFT */
-  NLOS_PASS_FK_XI = 6,         /* f-k pass 5: x-IFFT */
+  NLOS_PASS_FK_YI = 5,         /* f-k pass 5: y-IFFT */
+  NLOS_PASS_FK_XI = 6,         /* f-k pass 4: x-IFFT (runs before the y-IFFT) */
   NLOS_PASS_RSD_PHASOR = 7,    /* RSD: temporal DFT to the selected frequencies */
   NLOS_PASS_RSD_X = 8,         /* RSD: x-FFT of the padded phasor planes */
   NLOS_PASS_RSD_Y = 9,         /* RSD: y-FFT */
