@@ -172,3 +172,14 @@ def test_invariants_scale_shift_hermitian():
     S = ofk.forward(ofk.scale_and_pad(tau, 2))
     conj_flip = np.conj(S[(-np.arange(16)) % 16][:, (-np.arange(16)) % 16][:, :, (-np.arange(64)) % 64])
     assert np.max(np.abs(S - conj_flip)) < 1e-10 * np.abs(S).max()
+
+
+def test_scaling_weights_are_the_linspace_of_algorithm_1():
+    """Algorithm 1 scales the transient by linspace(0, 1, Nz) along t: weight 0 at the
+    first bin, 1 at the last (t / (nt - 1)); t / nt or (t + 1) / nt would not match."""
+    for nt in (2, 7, 256):
+        G = ofk.scale_and_pad(np.ones((1, 1, nt)), 1)
+        w = G[0, 0, :].real
+        assert np.max(np.abs(w - np.linspace(0.0, 1.0, nt))) < 1e-15
+        assert np.max(np.abs(w - np.arange(nt) / nt)) > 1e-3
+        assert np.max(np.abs(w - (np.arange(nt) + 1) / nt)) > 1e-3

@@ -184,3 +184,88 @@ def test_rel_l2_compares_complex_values_as_complex():
     a = np.array([1 + 1j, 2 - 1j])
     b = np.array([1 + 1j, 2 + 1j])
     assert rel_l2(a, b) == pytest.approx(2 / np.sqrt(7), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# the modality pair (sigma_s, sigma_t) and the calibration offset Delta of Eq. 4
+# ---------------------------------------------------------------------------
+
+
+def _rsd_complex(tau, cfg, p, depths, **kw):
+    _, _, field = orsd.rsd(tau, cfg.dx, cfg.dy, cfg.bin_ps, 2, p.freq_bins, p.weights, depths,
+                           return_complex=True, **kw)
+    return field
+
+
+@pytest.mark.parametrize("m", [3, 17])
+def test_delta_is_an_optical_path_offset(m):
+    """Eq. 4's factor exp(i kappa Delta) with Delta = m c dt multiplies phasor f by
+    exp(2 pi i k_f m / nt), which by the DFT shift theorem is the phasor of the transient
+    advanced by m bins: a calibration offset of the optical path is the same as removing
+    m bins of extra path from the measurement.  A flipped sign (advance by -m) or a
+    dropped Delta fails."""
+    cfg, tau, p, depths = _small_case(8, 5)
+    delta = m * cfg.c_dt
+    got = _rsd_complex(tau, cfg, p, depths, delta=delta)
+    ref = _rsd_complex(np.roll(tau, -m, axis=2), cfg, p, depths)
+    assert rel_l2(got, ref) < 1e-12
+    # planted mistakes in the oracle's inputs: the pin tells them apart
+    assert rel_l2(_rsd_complex(tau, cfg, p, depths, delta=-delta), ref) > 1e-2
+    assert rel_l2(_rsd_complex(tau, cfg, p, depths), ref) > 1e-2
+
+
+def test_sigma_t_is_a_depth_dependent_path_offset():
+    """With sigma_t = 1, Eq. 4 adds kappa d to the phase: at a depth on the bin grid,
+    d = j c dt, depth plane j equals the sigma_t = 0 plane of the transient advanced by j
+    bins (shift theorem), plane by plane."""
+    cfg, tau, p, _ = _small_case(8, 5)
+    js = [20, 45, 70]
+    depths = np.array([j * cfg.c_dt for j in js])
+    got = _rsd_complex(tau, cfg, p, depths, sigma_s=1, sigma_t=1)
+    for i, j in enumerate(js):
+        ref = _rsd_complex(np.roll(tau, -j, axis=2), cfg, p, depths[i:i + 1], sigma_s=1, sigma_t=0)
+        assert rel_l2(got[i], ref[0]) < 1e-12
+        # sigma_t dropped or of the wrong sign does not match
+        wrong = _rsd_complex(np.roll(tau, j, axis=2), cfg, p, depths[i:i + 1], sigma_s=1, sigma_t=0)
+        assert rel_l2(got[i], wrong[0]) > 1e-2
+
+
+def _non_confocal_point(cfg, pos):
+    """Noise-free transient of a point reflector lit from the wall point beneath it: the
+    illumination leg is z0, the return leg |p - x_s|, so a photon arrives at
+    (z0 + |p - x_s|) / c, with 1/|p - x_s|^2 falloff and a Gaussian pulse of 1 bin."""
+    xs, ys = scenes.scan_positions(cfg)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    R = np.sqrt((X - pos[0]) ** 2 + (Y - pos[1]) ** 2 + pos[2] ** 2)
+    tb = (pos[2] + R) / cfg.c_dt
+    t = np.arange(cfg.nt)
+    return np.exp(-0.5 * (t[None, None, :] - tb[:, :, None]) ** 2) / R[:, :, None] ** 2
+
+
+def test_non_confocal_point_reflector_focus():
+    """Modality (1, 1) of Section 4.3: the reflector focuses at its position and at the
+    depth plane nearest z0.  A dropped sigma_t (path R instead of R + d) or a flipped one
+    (R - d) puts the peak at another depth; the confocal phase 2R agrees with R + z0 at
+    the apex only, so its focus is far weaker than the matched kernel's."""
+    pos = (0.12, -0.1, 0.45)
+    cfg = scenes.small_config(16, 16, 256, bin_ps=32, depth_range=(0.3, 0.8), n_depth=24)
+    tau = _non_confocal_point(cfg, pos)
+    p = scenes.rsd_params(cfg)
+    depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
+
+    def peak(**kw):
+        vol, _ = orsd.rsd(tau, cfg.dx, cfg.dy, cfg.bin_ps, 2, p.freq_bins, p.weights, depths, **kw)
+        return argmax_index(vol)
+
+    d, y, x = peak(sigma_s=1, sigma_t=1)
+    assert abs(x - ((pos[0] + 0.5) / cfg.dx - 0.5)) <= 1
+    assert abs(y - ((pos[1] + 0.5) / cfg.dy - 0.5)) <= 1
+    d_true = (pos[2] - depths[0]) / (depths[1] - depths[0])
+    assert abs(d - d_true) <= 1
+    for kw in ({"sigma_s": 1, "sigma_t": 0}, {"sigma_s": 1, "sigma_t": -1}):
+        assert abs(peak(**kw)[0] - d_true) > 2
+
+    def top(**kw):
+        return orsd.rsd(tau, cfg.dx, cfg.dy, cfg.bin_ps, 2, p.freq_bins, p.weights, depths, **kw)[0].max()
+
+    assert top(sigma_s=1, sigma_t=1) > 2.0 * top(sigma_s=2, sigma_t=0)
