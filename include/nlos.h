@@ -211,6 +211,23 @@ nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
 nlos_status nlos_fk(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_vol,
                     float *d_img, void *d_ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nlos_fk with the same arguments and
+ * results (the same kernels and pass sequence, bitwise-equal outputs), whose workspace
+ * is the library's static device scratch instead of a caller or pool buffer.  The call
+ * allocates nothing and frees nothing.  The scratch is one file-scope device array of
+ * NLOS_STATIC_SCRATCH_BYTES per GPU, held from the library's first use on that GPU
+ * (nlos_create) until the process ends; its device address is looked up once per device.
+ * Plans whose workspace (nlos_fk_workspace_bytes) exceeds it return NLOS_ERR_UNSUPPORTED
+ * before anything is enqueued: 128 MiB holds e.g. 64 x 64 x 512 padded x2 in FP32 and
+ * 128 x 128 x 256 padded x2 in FP16/BF16.  Every call on a GPU shares that GPU's array and
+ * leaves its last contents there (nothing in it needs clearing between calls): calls that
+ * overlap on one GPU -- from two streams, contexts or threads -- race and give undefined
+ * results; order them (one stream, or events).  Per-pass timing does not cover it. */
+#define NLOS_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+nlos_status nlos_fk_noalloc(nlos_ctx *ctx, const nlos_fk_plan *plan, const float *d_tau, float *d_vol,
+                            float *d_img);
+
 /* ------------------------------------------------------------------------ */
 /* Phasor-field RSD with the radial kernel (Section 4.3; Algorithm 4)        */
 /* ------------------------------------------------------------------------ */

@@ -140,6 +140,7 @@ struct nlos_ctx {
   std::vector<hipEvent_t> spare;      // recycled events
   hipStream_t aux = nullptr;          // second stream of the mixture of experts
   hipEvent_t fork[3] = {nullptr, nullptr, nullptr};
+  void* scratch = nullptr;            // this device's static scratch (nlos_fk_noalloc)
 };
 
 struct nlos_fk_plan {
@@ -304,6 +305,12 @@ nlos_status nlos_create(int device, void* hip_stream, nlos_ctx** out) {
   if (!c) return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: host allocation");
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // the static scratch's device address on this device (looked up once per device)
+  const hipError_t se = nlos::static_scratch_address(device, &c->scratch);
+  if (se != hipSuccess) {
+    delete c;
+    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: static scratch address: %s", hipGetErrorString(se));
+  }
   // W_2048^k = exp(-2 pi i k / 2048) in double with exact octant reduction, stored as float
   std::vector<float2> tw(nlos::kTwiddleTableN);
   for (int k = 0; k < nlos::kTwiddleTableN; ++k) {
@@ -716,6 +723,31 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   st = get_workspace(ctx, d_ws, ws_bytes, need, &ws);
   if (st != NLOS_OK) return st;
   return fk_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ws);
+}
+
+nlos_status nlos_fk_noalloc(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, float* d_vol, float* d_img) {
+  if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: ctx or plan is NULL");
+  if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: d_tau is NULL");
+  if (reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: d_tau must be 8-byte aligned");
+  if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: d_vol and d_img are both NULL");
+  if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: plan of another device");
+  size_t need = 0;
+  nlos_status st = nlos_fk_workspace_bytes(&p->d, &need);
+  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+  if (need > nlos::kStaticScratchBytes)
+    return fail(ctx, NLOS_ERR_UNSUPPORTED,
+                "nlos_fk_noalloc: this reconstruction needs %zu bytes of workspace, more than the %zu bytes of "
+                "static scratch (use nlos_fk)",
+                need, nlos::kStaticScratchBytes);
+  if (!ctx->scratch) return fail(ctx, NLOS_ERR_DEVICE, "nlos_fk_noalloc: no static scratch on device %d", ctx->device);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // per-pass timing would create HIP events: it is suspended for this call
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  st = fk_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ctx->scratch);
+  ctx->timing = timing;
+  return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -152,6 +152,12 @@ constexpr int kScaleBlocks = 1024;
 hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
                             int l_norm, int l_my, int l_mx, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
+
+// Static device scratch of the allocation-free entry points (k_scratch.hip): its size,
+// and its device address on `device` (looked up once per device with that device
+// current, then cached; the array's name itself is never passed to a kernel).
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+hipError_t static_scratch_address(int device, void** out);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
 hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,

@@ -89,6 +89,7 @@ _SIGNATURES = {
     "nlos_fk_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(_VP)]),
     "nlos_fk_plan_destroy": (_ST, [_VP]),
     "nlos_fk": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
+    "nlos_fk_noalloc": (_ST, [_VP, _VP, _VP, _VP, _VP]),
     "nlos_rsd_check": (_ST, [ctypes.POINTER(nlos_rsd_desc)]),
     "nlos_rsd_geometry_get": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(nlos_rsd_geometry)]),
     "nlos_rsd_kernel_host": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_float),
@@ -274,6 +275,13 @@ def nlos_fk(ctx: int, plan: int, tau, vol=None, img=None, ws=None) -> None:
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().nlos_fk(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img), _ptr(ws), ws_bytes),
            "nlos_fk", ctx)
+
+
+NLOS_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def nlos_fk_noalloc(ctx: int, plan: int, tau, vol=None, img=None) -> None:
+    _check(lib().nlos_fk_noalloc(ctx, plan, _ptr(tau), _ptr(vol), _ptr(img)), "nlos_fk_noalloc", ctx)
 
 
 # ---------------------------------------------------------------------------
