@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -141,6 +142,9 @@ struct nlos_ctx {
   hipStream_t aux = nullptr;          // second stream of the mixture of experts
   hipEvent_t fork[3] = {nullptr, nullptr, nullptr};
   void* scratch = nullptr;            // this device's static scratch (nlos_fk_noalloc)
+  void* d_mfma = nullptr;             // matrix-core DFT operands (FP64-built)
+  nlos::MfmaTables mt{};
+  bool mfma = true;                   // four-byte f-k passes on the matrix cores
 };
 
 struct nlos_fk_plan {
@@ -327,6 +331,15 @@ nlos_status nlos_create(int device, void* hip_stream, nlos_ctx** out) {
     delete c;
     return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: twiddle upload failed");
   }
+  const hipError_t me = nlos::mfma_tables_create(device, &c->d_mfma, &c->mt);
+  if (me != hipSuccess) {
+    (void)hipFree(c->d_tw);
+    delete c;
+    return fail(nullptr, me == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
+                "nlos_create: matrix-core operand tables: %s", hipGetErrorString(me));
+  }
+  const char* mf = std::getenv("NLOS_FK_MFMA");
+  c->mfma = !(mf && mf[0] == '0');
   *out = c;
   return NLOS_OK;
 }
@@ -337,6 +350,7 @@ nlos_status nlos_destroy(nlos_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->pool) (void)hipFree(ctx->pool);
   if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+  if (ctx->d_mfma) (void)hipFree(ctx->d_mfma);
   for (auto& t : ctx->recs) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -647,7 +661,10 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   a.in_plane = nt; a.in_line = RH; a.out_plane = nt; a.out_line = RH;
   a.ncols = (int)nt; a.n_in = (int)ny; a.n_out = (int)My;
   a.e_in = ex; a.e_out = ex;
+  const bool mf = ctx->mfma && sp != nlos::SP_F32;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_Y, [&] {
+    if (mf && nlos::mfma_strided_ok((int)My, sp, a))
+      return nlos::launch_strided_mfma((int)My, false, a, (int)(Mx / 2 + 1), ctx->mt, tw, s, sp);
     return p->gen_y ? nlos::launch_gen_strided(p->gy, false, nlos::ST_C64, a, (int)(Mx / 2 + 1), s)
                     : nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)(Mx / 2 + 1), tw, s, sp, true);
   }));
@@ -660,6 +677,10 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   c.sxk = p->sxk; c.syk = p->syk; c.norm = p->norm;
   c.e_in = ex; c.e_out = ex ? ex + 1 : nullptr;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_COLUMN, [&] {
+    // FP16 stores the remapped spectrum times 2^(e_in + log2(Mx My Mt)): the 1/(Mx My Mt)
+    // and the exponent change cancel
+    if (mf && nlos::mfma_column_ok(p->Mt, (int)nt, sp, c))
+      return nlos::launch_fk_column_pair_mfma(c, ctx->mt, tw, sp == nlos::SP_F16 ? 1.0f : p->norm, s, sp);
     return p->gen_t ? nlos::launch_gen_column_pair(p->gt, c, s) : nlos::launch_fk_column_pair(p->Mt, c, tw, s, sp);
   }));
   // The x-IFFT runs first: it walks W3's rows 4 KB apart, which runs faster than the
@@ -672,6 +693,8 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   a.ncols = (int)nt; a.n_in = (int)Mx; a.n_out = (int)nx;
   a.e_in = ex ? ex + 1 : nullptr; a.e_out = ex ? ex + 2 : nullptr;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_XI, [&] {
+    if (mf && nlos::mfma_strided_ok((int)Mx, sp, a))
+      return nlos::launch_strided_mfma((int)Mx, true, a, (int)My, ctx->mt, tw, s, sp);
     return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64, a, (int)My, s)
                     : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64, a, (int)My, tw, s, sp, true);
   }));
@@ -682,6 +705,8 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
   a.ncols = (int)nt; a.n_in = (int)My; a.n_out = (int)ny;
   a.e_in = ex ? ex + 2 : nullptr; a.e_out = ex ? ex + 3 : nullptr;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_YI, [&] {
+    if (mf && nlos::mfma_strided_ok((int)My, sp, a))
+      return nlos::launch_strided_mfma((int)My, true, a, (int)nx, ctx->mt, tw, s, sp);
     return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)nx, s)
                     : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)nx, tw, s, sp, true);
   }));
@@ -700,6 +725,7 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
     return NLOS_OK;
   }
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_ZI, [&] {
+    if (mf && nlos::mfma_zfft_ok(p->Mt, sp, z)) return nlos::launch_zfft_abs2_mfma(z, ctx->mt, tw, s, sp);
     return p->gen_t ? nlos::launch_gen_contig(p->gt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, s)
                     : nlos::launch_contig(p->Mt, true, nlos::CL_C64, nlos::CS_ABS2_MAX, z, tw, s, sp);
   }));

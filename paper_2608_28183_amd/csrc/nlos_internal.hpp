@@ -153,6 +153,33 @@ hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partia
                             int l_norm, int l_my, int l_mx, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
 
+// Constant operands of the matrix-core DFT stages (mfma_fft.hpp), per context, indexed
+// [inverse][scaled by 1/R][0 binary16, 1 bfloat16]; 64 lanes x 16 bytes per operand.
+//   a16: radix-16 DFT matrix as the A operand (outputs along rows), 2 operands (K steps);
+//   a32: radix 32 as A, 8 operands: output block b (outputs 16 b..16 b + 15), K step q at b * 4 + q;
+//   b32: radix 32 as the B operand (outputs along columns), 8 operands: part c (0 re,
+//        1 im) of outputs 0..31, K step q at c * 4 + q.
+struct MfmaTables {
+  const void* a16[2][2][2];
+  const void* a32[2][2][2];
+  const void* b32[2][2][2];
+};
+hipError_t mfma_tables_create(int device, void** d_buf, MfmaTables* t);
+
+// Matrix-core passes of the four-byte f-k storage (k_mfma.hip) and the shapes they take:
+// strided lines of 256 or 512 points over a multiple of 32 columns with n_in, n_out in
+// {N/2, N}; 1024-point columns with 512 stored samples.  FP16 inverse strided passes
+// return values carrying 2^-log2(N) times their input's factor (the next intermediate's).
+bool mfma_strided_ok(int n, int sp, const StridedArgs& a);
+hipError_t launch_strided_mfma(int n, bool inverse, const StridedArgs& a, int nplanes, const MfmaTables& t,
+                               const float2* tw, hipStream_t s, int sp);
+bool mfma_column_ok(int mt, int nt, int sp, const FkPairArgs& a);
+// oscale: 1/(Mx My Mt) times 2^(e_out - e_in) (FP16: 1; BF16: 1/(Mx My Mt))
+hipError_t launch_fk_column_pair_mfma(const FkPairArgs& a, const MfmaTables& t, const float2* tw, float oscale,
+                                      hipStream_t s, int sp);
+bool mfma_zfft_ok(int mt, int sp, const ContigArgs& a);
+hipError_t launch_zfft_abs2_mfma(const ContigArgs& a, const MfmaTables& t, const float2* tw, hipStream_t s, int sp);
+
 // Static device scratch of the allocation-free entry points (k_scratch.hip): its size,
 // and its device address on `device` (looked up once per device with that device
 // current, then cached; the array's name itself is never passed to a kernel).

@@ -100,3 +100,24 @@ def test_fk_reduced_deterministic(ctx, prec):
     v1, i1 = run_fk(ctx, tau, prec=prec)
     v2, i2 = run_fk(ctx, tau, prec=prec)
     assert np.array_equal(v1, v2) and np.array_equal(i1, i2)
+
+
+# shapes on the matrix-core passes: strided lines of 256 and 512 points (forward with
+# zero-padded inputs, inverse with cropped outputs, and unpadded), 1024-point columns with
+# 512 stored samples (column pass, z-IFFT)
+MFMA_SHAPES = [(128, 8, 512, 2), (8, 128, 512, 2), (16, 256, 64, 2), (256, 16, 64, 2),
+               (256, 256, 32, 1), (32, 32, 512, 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape", MFMA_SHAPES)
+def test_fk_reduced_matrix_core_shapes(ctx, shape, prec):
+    ny, nx, nt, pad = shape
+    say("fk matrix-core", prec, shape)
+    rng = np.random.default_rng(ny * 17 + nx * 3 + nt + pad)
+    tau = rng.poisson(3.0, size=(ny, nx, nt)).astype(np.float32)
+    ww, wh, bps = 0.5 + 0.01 * nx, 0.4 + 0.01 * ny, 24.0
+    vol, img = run_fk(ctx, tau, ww, wh, bps, pad, prec=prec)
+    rv, ri = ofk.fk(tau.astype(np.float64), ww, wh, bps, pad)
+    say("  rel_l2 vol %.3e img %.3e" % (rel_l2(vol, rv), rel_l2(img, ri)))
+    assert rel_l2(vol, rv) < tol(prec) and rel_l2(img, ri) < tol(prec)
