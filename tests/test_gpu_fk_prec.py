@@ -1,16 +1,18 @@
 """GPU accuracy of the reduced-precision f-k path (Section 4.2, data quantization).
 
-FP16 / BF16 hold the five complex intermediates at four bytes per value; arithmetic is
-FP32.  BF16 is stored as is; FP16 is stored times a power of two per intermediate,
-computed on the device from a bound on its magnitude.  Each intermediate is rounded once
-when stored, to a relative error of at most u (2^-11 for FP16, 2^-8 for BF16) per
-element (FP16 values that the scaling leaves subnormal are too small to matter in L2:
-the bound exceeds the RMS of an intermediate by at most 2^23).  The forward and inverse
-DFTs are unitary up to their scale and the Stolt remap is a linear interpolation times
-kz/q <= 1, so five roundings leave Psi within about 5 u in relative L2 and |Psi|^2
-within about 10 u: the bound used here (4.9e-3 for FP16, 3.9e-2 for BF16).  The paper
-reports 57 dB image PSNR for its FP16 f-k against FP32; FP16 here is held to that level
-on the image against the FP64 oracle.
+FP16 / BF16 hold the five complex intermediates at four bytes per value.  BF16 is stored
+as is; FP16 is stored times a power of two per intermediate, computed on the device from
+a bound on its magnitude.  Where the line lengths allow (strided lines of 256 or 512
+points, 1024-point columns) the DFT stages run on the matrix cores: products of the
+stored values with a constant DFT matrix rounded to the same format, accumulated in FP32,
+the intermediate between the two products rounded to the format once more.  Each such
+rounding is a relative error of at most u per element (2^-11 for FP16, 2^-8 for BF16;
+FP16 values that the scaling leaves subnormal are too small to matter in L2: the bound
+exceeds the RMS of an intermediate by at most 2^23).  The DFTs are unitary up to their
+scale and the Stolt remap is a linear interpolation times kz/q <= 1, so |Psi|^2 stays
+within about 10 u in relative L2: the bound used here (4.9e-3 for FP16, 3.9e-2 for BF16).
+The paper reports 57 dB image PSNR for its FP16 f-k against FP32; FP16 here is held to
+that level on the image against the FP64 oracle.
 """
 import numpy as np
 import pytest
