@@ -130,11 +130,11 @@ def cpu_baseline_fk(cfg, fraction=2):
     return t_total * fraction, t_total
 
 
-def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=5005):
+def serve_bench(n_requests=2000, rate_hz=50.0, n_slots=4, budget_gib=24, seed=5005, n_saturation=1000):
     """Poisson stream of mixed reconstructions through the continuous-batching loop:
     shapes uniform over {64x64x512, 128x128x1024, 256x256x512}, f-k / RSD 50/50; runs
-    all FP32, all FP16 and 50/50 mixed, and a saturation run (all requests at 2000/s)
-    under a 16 GiB budget."""
+    all FP32, all FP16 and 50/50 mixed (2000 requests each, about 40 s at 50/s), and a
+    saturation run (1000 requests at 2000/s) under a 16 GiB budget."""
     import torch
 
     import scenes
@@ -167,13 +167,50 @@ def serve_bench(n_requests=200, rate_hz=50.0, n_slots=4, budget_gib=24, seed=500
     one_run(("fp32",), 1000.0, budget_gib, 12)  # warm-up: allocator pools, code paths
     return {
         "arrival_rate_hz": rate_hz, "requests": n_requests, "slots": n_slots,
+        "saturation_requests": n_saturation,
         "mix": "shapes uniform over 64x64x512, 128x128x1024, 256x256x512; f-k/RSD 50/50; "
                "fp16 = FP16 f-k intermediates, FP16 RSD kernel",
         "fp32": one_run(("fp32",), rate_hz, budget_gib, n_requests),
         "fp16": one_run(("fp16",), rate_hz, budget_gib, n_requests),
         "fp32_fp16_mixed": one_run(("fp32", "fp16"), rate_hz, budget_gib, n_requests),
-        "saturation_2000hz_16GiB": one_run(("fp32",), 2000.0, 16, 100),
+        "saturation_2000hz_16GiB": one_run(("fp32",), 2000.0, 16, n_saturation),
     }
+
+
+def per_call_ms(step, n, stream):
+    """Durations of n back-to-back calls, each bracketed by HIP events on the launch stream."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    import numpy as np
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"calls": n, "p50_ms": round(float(np.percentile(t, 50)), 4),
+            "p99_ms": round(float(np.percentile(t, 99)), 4), "mean_ms": round(float(t.mean()), 4)}
+
+
+def golden_accuracy(name, vol, img):
+    """Error of a full-size output against the FP64 oracle values stored under tests/golden/
+    (written by tests/golden/make_golden.py from the oracle): the whole max-over-depth
+    image and 4096 sampled voxels (the 1024 largest and 3072 random), relative L2, max
+    |error| / max |reference| and whether the image arg-max agrees."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    im = img.detach().cpu().numpy().astype(np.float64)
+    v = vol.detach().reshape(-1)[__import__("torch").from_numpy(g["idx"]).to(vol.device)].cpu().numpy()
+    ri, rv = g["img"].astype(np.float64), g["val"]
+
+    def rl2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"img_rel_l2": rl2(im, ri), "img_max_rel": float(np.abs(im - ri).max() / np.abs(ri).max()),
+            "sampled_voxels_rel_l2": rl2(v, rv), "sampled_voxels_max_rel": float(np.abs(v - rv).max() / np.abs(rv).max()),
+            "img_argmax_equal": bool(np.argmax(im) == np.argmax(ri)), "reference": "FP64 oracle"}
 
 
 def copy_calibration(args):
@@ -427,6 +464,41 @@ def main():
     print(f"[bench] {args.steps} steps: {sec*1e3:.3f} ms/step; passes (avg ms): "
           + ", ".join(f"{k} {v:.3f}" for k, v in avg_ms.items()), file=sys.stderr, flush=True)
 
+    # per-call latency of the step (HIP events around each call, back to back)
+    per_call = per_call_ms(step, max(100, args.steps), stream)
+    accuracy = None
+    precision_path = None
+    if kind == "fk":
+        step()
+        torch.cuda.synchronize()
+        accuracy = golden_accuracy(f"fk_{cname}", vol, img)
+        if args.prec == "fp32":
+            # the reduced-precision storage forms of the same step (FP16 / BF16 intermediates,
+            # DFT stages on the matrix cores): volumes/s, per-call latency and accuracy
+            precision_path = {}
+            for pr in ("fp16", "bf16"):
+                pp = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad, pr)
+                pws = pp.workspace()
+                pstep = lambda: pp(tau, vol, img, pws)  # noqa: E731
+                for _ in range(args.warmup):
+                    pstep()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    pstep()
+                torch.cuda.synchronize()
+                psec = (time.perf_counter() - t0) / args.steps
+                pc = per_call_ms(pstep, max(100, args.steps), stream)
+                pstep()
+                torch.cuda.synchronize()
+                precision_path[pr] = {"value": round(1.0 / psec, 3), "unit": unit, "ms_per_step": round(psec * 1e3, 4),
+                                      "speedup_vs_fp32": round(sec / psec, 3),
+                                      "step_bytes": sum(fk_pass_bytes(ny, nx, nt, cfg.pad, 4).values()),
+                                      "per_call": pc, "accuracy": golden_accuracy(f"fk_{cname}", vol, img)}
+                del pws
+            step()  # leave the FP32 result in vol / img
+            torch.cuda.synchronize()
+
     cpu = None
     if not args.no_cpu_baseline and kind == "fk":
         try:
@@ -498,6 +570,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.prec == "fp32" else args.prec, "data": "synthetic",
         "config": workload, "roofline": roofline, "cpu_baseline": cpu,
+        "per_call": per_call, "accuracy": accuracy, "precision_path": precision_path,
         "passes_ms": {k: round(v, 4) for k, v in avg_ms.items()},
         "serving": serving,
         "moe_vs_separate": moe_cmp,
