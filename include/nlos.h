@@ -190,11 +190,16 @@ typedef struct {
  * (NLOS_FP16 / NLOS_BF16 there: NLOS_ERR_UNSUPPORTED); results meet the same FP32
  * accuracy as power-of-two grids. */
 nlos_status nlos_fk_check(const nlos_fk_desc *desc);
-/* Exact device workspace one nlos_fk call needs (host only): about half the FP32
- * figure for NLOS_FP16 / NLOS_BF16 (FP16 adds 4.3 KB of scale scratch). */
-nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc *desc, size_t *bytes);
+/* Exact device workspace one nlos_fk call with a plan of this descriptor needs (host
+ * only, no plan required): about half the FP32 figure for NLOS_FP16 / NLOS_BF16 (FP16 adds
+ * 4.3 KB of scale scratch). */
+nlos_status nlos_fk_desc_workspace_bytes(const nlos_fk_desc *desc, size_t *bytes);
 nlos_status nlos_fk_plan_create(nlos_ctx *ctx, const nlos_fk_desc *desc, nlos_fk_plan **out);
 nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
+/* Exact device workspace one nlos_fk call on plan needs (host only; the same figure as
+ * nlos_fk_desc_workspace_bytes of the plan's descriptor).  This is the size the serving
+ * loop admits requests against. */
+nlos_status nlos_fk_workspace_bytes(const nlos_fk_plan *plan, size_t *bytes);
 
 /* f-k migration of d_tau[ny][nx][nt] (float32 counts):
  *   g = tau * t/(nt-1), zero-padded to My x Mx x Mt (M = pad * n);
@@ -204,7 +209,7 @@ nlos_status nlos_fk_plan_destroy(nlos_fk_plan *plan);
  *   frequency sample; inverse 3D DFT normalised by 1/(Mx My Mt).
  * Writes d_vol[ny][nx][nt] = |Psi|^2 on the unpadded grid and d_img[ny][nx] =
  * max over depth of d_vol; either output may be NULL (not both).  d_ws is
- * 256-byte aligned device workspace of ws_bytes >= nlos_fk_workspace_bytes
+ * 256-byte aligned device workspace of ws_bytes >= nlos_fk_workspace_bytes(plan)
  * (NULL: the context pool is used and grown as needed; misaligned:
  * NLOS_ERR_INVALID_ARG; too small: NLOS_ERR_OUT_OF_MEMORY).  d_tau must be 8-byte
  * aligned.  Inputs are not modified. */
@@ -247,6 +252,10 @@ typedef struct {
   double delta_m;          /* calibration offset of the optical path (m) */
   nlos_precision data_prec;   /* storage of the complex intermediates */
   nlos_precision kernel_prec; /* storage of the radial kernel K_r */
+  int vol_depth_major;        /* layout of nlos_rsd's d_vol: 0 [ny][nx][n_depth] (depth
+                                 contiguous, like the time axis of the transient); 1
+                                 [n_depth][ny][nx] (a stack of depth planes), written by one
+                                 more pass over the volume */
 } nlos_rsd_desc;
 
 /* Radial sampling of the supplementary material: r_max, rho_max, ring count
@@ -270,22 +279,25 @@ nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc *desc, nlos_rsd_geometry *
  * stores it as float (re, im) into out[n_rho][n_freq][n_depth][2]; n_floats must
  * be at least 2 * n_rho * n_freq * n_depth. */
 nlos_status nlos_rsd_kernel_host(const nlos_rsd_desc *desc, float *out, size_t n_floats);
-/* Exact device workspace one nlos_rsd call needs (host only). */
-nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc *desc, size_t *bytes);
+/* Exact device workspace one nlos_rsd call with a plan of this descriptor needs (host
+ * only, no plan required). */
+nlos_status nlos_rsd_desc_workspace_bytes(const nlos_rsd_desc *desc, size_t *bytes);
 /* Builds K_r (Eq. 4-6, FP64 on the host, stored per kernel_prec), the pixel lookup
  * (radius map -> taper, interpolation bins and weights of Listing 3, pixels grouped by
  * radial bin) and the frequency tables, and uploads them to HBM. */
 nlos_status nlos_rsd_plan_create(nlos_ctx *ctx, const nlos_rsd_desc *desc, nlos_rsd_plan **out);
 nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan *plan);
+/* Exact device workspace one nlos_rsd call on plan needs (host only). */
+nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_plan *plan, size_t *bytes);
 
 /* Radial RSD of d_tau[ny][nx][nt] (float32):
  *   P[f] = sum_t tau e^{-2 pi i k_f t / nt};  P^ = DFT2(P padded top-left);
  *   C[d](u,v) = sum_f w_f P^[f](u,v) a(rho) lerp(K_r[., f, d], rho(u,v)) with the
  *   smoothstep taper a over the last 8 radial bins below the cutoff;
  *   I[d] = IDFT2(C[d]) normalised by 1/(Mx My).
- * Writes d_vol[ny][nx][n_depth] = |I| on the unpadded grid (depth contiguous, like
- * the time axis of the transient) and d_img[ny][nx] = max over depth; either may be
- * NULL (not both).  Workspace as for nlos_fk. */
+ * Writes d_vol = |I| on the unpadded grid, [ny][nx][n_depth] (depth contiguous, like the
+ * time axis of the transient) or, with desc->vol_depth_major, [n_depth][ny][nx], and
+ * d_img[ny][nx] = max over depth; either may be NULL (not both).  Workspace as for nlos_fk. */
 nlos_status nlos_rsd(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
                      float *d_img, void *d_ws, size_t ws_bytes);
 /* nlos_rsd from phasors already at the plan's frequencies: d_phasor[ny][nx][n_freq]

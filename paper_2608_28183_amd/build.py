@@ -62,6 +62,53 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host sanitizers for the host-side sources (validation, plans, the C boundary): every
+# -fsanitize= applies to the host compilation only (-Xarch_host), the device code is the
+# regular build's.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+SAN_LIB = os.path.join(ROOT, "_build", "libnlos_san.so")
+SAN_BUILD = os.path.join(ROOT, "_build", "san")
+
+
+def sanitizer_runtime() -> str:
+    """clang's shared AddressSanitizer runtime (with the UBSan handlers), to LD_PRELOAD."""
+    import glob
+    libs = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not libs:
+        raise RuntimeError("clang's AddressSanitizer runtime not found")
+    return libs[-1]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """_build/libnlos_san.so: the host .cpp sources with AddressSanitizer and UBSan, the
+    kernel objects of the regular build (run build() first)."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    objs = []
+    for f in sorted(os.listdir(CSRC)):
+        src = os.path.join(CSRC, f)
+        if f.endswith(".cpp"):
+            obj = os.path.join(SAN_BUILD, f + ".o")
+            cmd = [hipcc(), *COMMON, *SAN_FLAGS, "-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+            objs.append(obj)
+        elif f.endswith(".hip"):
+            obj = os.path.join(BUILD, f + ".o")
+            if not os.path.exists(obj):
+                raise RuntimeError(f"{obj} missing: run the regular build first")
+            objs.append(obj)
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", SAN_LIB, "-lpthread",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {SAN_LIB}")
+    return SAN_LIB
+
+
 def source_sha() -> str:
     """sha256 over the kernel and host sources (identifies the built code)."""
     import hashlib
@@ -74,5 +121,8 @@ def source_sha() -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "sanitized":
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -121,6 +121,34 @@ __device__ __forceinline__ void stolt_pair(int kz, int half, double A, float nor
   }
 }
 
+// The same remap from a natural-order spectrum sp[0..n] whose sp[n] repeats bin 0, so that
+// both taps of the column (i0, i0 + 1) and of its mirror (n - 1 - i0, n - i0) are plain
+// adjacent reads: at q = half - 1 exactly the weight of the second tap is zero.
+__device__ __forceinline__ void stolt_pair_nat(int kz, int half, int n, double A, float norm, const float2* sp,
+                                               float2& xa, float2& xb) {
+  xa = make_float2(0.f, 0.f);
+  xb = make_float2(0.f, 0.f);
+  if (kz > 0 && kz < half) {
+    const double q2 = A + double(kz * kz);
+    const float qf = __builtin_amdgcn_sqrtf((float)q2);
+    const float rq = __builtin_amdgcn_rcpf(qf);
+    const double q0 = (double)qf;
+    const double q = fma((double)(0.5f * rq), fma(-q0, q0, q2), q0);
+    if (q <= double(half - 1)) {
+      const double fl = floor(q);
+      const int i0 = int(fl);
+      const float fr = float(q - fl);
+      const float jac = float(kz) * rq * norm;
+      const float2 s0 = sp[i0], s1 = sp[i0 + 1];
+      const float2 m1 = sp[n - 1 - i0], m0 = sp[n - i0];
+      xa.x = fmaf(fr, s1.x - s0.x, s0.x) * jac;
+      xa.y = fmaf(fr, s1.y - s0.y, s0.y) * jac;
+      xb.x = fmaf(fr, m1.x - m0.x, m0.x) * jac;
+      xb.y = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
+    }
+  }
+}
+
 // PADDED: the column's upper half is the zero padding (nt = N/2), known at compile time,
 // so the zero inputs fold out of the first radix stage.
 template <int N, int E_ = default_e(N), int SP = SP_F32, bool TSCALE = false, bool PADDED = false>
@@ -177,11 +205,16 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
       }
     }
     __syncthreads();  // the previous item's last LDS reads are done
-    fft_run<S, false, true>(v, p, my, idx, tw, [&](int n, float2 val) { my[swz(n)] = val; });
+    // the spectrum in natural order (the line stride leaves room for the repeated bin 0)
+    static_assert(C::LSTRIDE > N, "room for bin N");
+    fft_run<S, false, true>(v, p, my, idx, tw, [&](int n, float2 val) {
+      my[n] = val;
+      if (n == 0) my[N] = val;
+    });
     __syncthreads();
 
-    // Stolt (shared by the pair): q = sqrt(A + kz^2) in t-bin units from a float square
-    // root refined by one FP64 Newton step; lerp weight, Jacobian kz/q, 1/(Mx My Mt).
+    // Stolt (shared by the pair): q = sqrt(A + kz^2) in t-bin units; lerp weight,
+    // Jacobian kz/q, 1/(Mx My Mt).
     const int kxs = it.kx < a.Mx / 2 ? it.kx : it.kx - a.Mx;
     const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
     const double ax = a.sxk * kxs, ay = a.syk * kys;
@@ -197,9 +230,7 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
 #pragma unroll 2
     for (int kz = p; kz < a.nt; kz += P) {
       float2 xa, xb;
-      stolt_pair(
-          kz, HALF, A, a.norm, [&](int i) { return my[swz(i)]; },
-          [&](int i) { return my[swz((N - i) & (N - 1))]; }, xa, xb);
+      stolt_pair_nat(kz, HALF, N, A, a.norm, my, xa, xb);
       if constexpr (SP == SP_F16) {
         xa = ldexp2(xa, ex);
         xb = ldexp2(xb, ex);

@@ -246,7 +246,14 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
       const int kxs = it.kx < a.Mx / 2 ? it.kx : it.kx - a.Mx;
       const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
       const double ax = a.sxk * kxs, ay = a.syk * kys;
-      const float A = (float)(ax * ax + ay * ay);
+      const double Ad = ax * ax + ay * ay;
+      const float A = (float)Ad;
+      // the last kz inside the frequency grid, q = sqrt(A + kz^2) <= HALF - 1, decided in FP64
+      // once per column as in the FP64 definition (an FP32 q^2 can flip it for tiny A)
+      const double rem = double((HALF - 1) * (HALF - 1)) - Ad;
+      int kzmax = rem < 0.0 ? -1 : (int)sqrt(rem);
+      if (kzmax >= 0 && double(kzmax) * kzmax > rem) --kzmax;
+      if (double(kzmax + 1) * (kzmax + 1) <= rem) ++kzmax;
       unsigned int* o1 = outb + (long long)it.ky * a.out_row + (long long)it.kx * a.nt + lane;
       unsigned int* o2 = outb + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt + lane;
       const bool ok1 = ok[u], ok2 = ok[u] && it.has_mirror;
@@ -256,8 +263,11 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
         const float q2 = fmaf(kz, kz, A);
         const float rq = __builtin_amdgcn_rsqf(q2);
         const float qv = q2 * rq;
-        const bool inside = qv <= (float)(HALF - 1);
-        const float qc = fminf(qv, (float)(HALF - 1));  // a NaN (kz = 0 at kx = ky = 0) gives HALF - 1
+        // q is clamped to HALF - 1 (a NaN, kz = 0 at kx = ky = 0, also gives HALF - 1, with a
+        // zero Jacobian)
+        const int kzi = lane + 64 * i;
+        const bool inside = kzi > 0 && kzi <= kzmax;
+        const float qc = fminf(qv, (float)(HALF - 1));
         const float fl = floorf(qc);
         const int i0 = (int)fl;
         const float fr = qc - fl;

@@ -88,7 +88,7 @@ hipError_t mfma_tables_create(int device, void** d_buf, MfmaTables* t) {
       }
   *d_buf = nullptr;
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipMalloc(d_buf, h.size() * sizeof(uint16_t));
+  if (e == hipSuccess) e = dev_alloc(d_buf, h.size() * sizeof(uint16_t));
   if (e != hipSuccess) return e;
   e = hipMemcpy(*d_buf, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

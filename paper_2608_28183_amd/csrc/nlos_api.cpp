@@ -1,10 +1,12 @@
 // Host side of libnlos: contexts, plans, validation, plan-time tables and the
 // pass schedules of nlos_bin / nlos_fk / nlos_rsd.  See include/nlos.h.
 #include "nlos.h"
+#include "nlos_debug.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,6 +24,32 @@ using nlos::ContigArgs;
 using nlos::FkPairArgs;
 using nlos::FkXArgs;
 using nlos::StridedArgs;
+
+namespace nlos {
+
+std::atomic<int> g_fail_allocs{0};
+namespace {
+bool take_injected_failure() {
+  int n = g_fail_allocs.load();
+  while (n > 0)
+    if (g_fail_allocs.compare_exchange_weak(n, n - 1)) return true;
+  return false;
+}
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  if (take_injected_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void host_alloc_point() {
+  if (take_injected_failure()) throw std::bad_alloc();
+}
+
+}  // namespace nlos
 
 namespace {
 
@@ -63,7 +91,7 @@ hipError_t gen_tables(int device, const int* m, const bool* use, nlos::GenPlan* 
   *d_tw = nullptr;
   if (tw.empty()) return hipSuccess;
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipMalloc(d_tw, tw.size() * sizeof(float2));
+  if (e == hipSuccess) e = nlos::dev_alloc((void**)d_tw, tw.size() * sizeof(float2));
   if (e != hipSuccess) return e;
   if ((e = hipMemcpy(*d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) {
     (void)hipFree(*d_tw);
@@ -241,6 +269,8 @@ static const char* const kPassNames[NLOS_PASS_COUNT] = {
 
 extern "C" {
 
+void nlos_debug_fail_allocations(int n) { nlos::g_fail_allocs.store(n > 0 ? n : 0); }
+
 int nlos_version(void) { return 100; }
 
 const char* nlos_pass_name(int pass) {
@@ -297,51 +327,56 @@ const char* nlos_last_error(const nlos_ctx* ctx) { return ctx ? ctx->err.c_str()
 // ---------------------------------------------------------------------------
 
 nlos_status nlos_create(int device, void* hip_stream, nlos_ctx** out) {
-  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: out is NULL");
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
-    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: no HIP device");
-  if (device < 0 || device >= count)
-    return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: device %d of %d", device, count);
-  if (hipSetDevice(device) != hipSuccess)
-    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: hipSetDevice(%d) failed", device);
-  nlos_ctx* c = new (std::nothrow) nlos_ctx();
-  if (!c) return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: host allocation");
-  c->device = device;
-  c->stream = static_cast<hipStream_t>(hip_stream);
-  // the static scratch's device address on this device (looked up once per device)
-  const hipError_t se = nlos::static_scratch_address(device, &c->scratch);
-  if (se != hipSuccess) {
-    delete c;
-    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: static scratch address: %s", hipGetErrorString(se));
+  try {
+    if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+      return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: no HIP device");
+    if (device < 0 || device >= count)
+      return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_create: device %d of %d", device, count);
+    if (hipSetDevice(device) != hipSuccess)
+      return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: hipSetDevice(%d) failed", device);
+    nlos::host_alloc_point();
+    nlos_ctx* c = new (std::nothrow) nlos_ctx();
+    if (!c) return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: host allocation");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    // the static scratch's device address on this device (looked up once per device)
+    const hipError_t se = nlos::static_scratch_address(device, &c->scratch);
+    if (se != hipSuccess) {
+      delete c;
+      return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: static scratch address: %s", hipGetErrorString(se));
+    }
+    // W_2048^k = exp(-2 pi i k / 2048) in double with exact octant reduction, stored as float
+    std::vector<float2> tw(nlos::kTwiddleTableN);
+    for (int k = 0; k < nlos::kTwiddleTableN; ++k) {
+      double cs, sn;
+      nlos::cos_sin_2pi_frac(k, nlos::kTwiddleTableN, &cs, &sn);
+      tw[k] = make_float2((float)cs, (float)-sn);
+    }
+    if (nlos::dev_alloc((void**)&c->d_tw, tw.size() * sizeof(float2)) != hipSuccess) {
+      delete c;
+      return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: twiddle table allocation");
+    }
+    if (hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(c->d_tw);
+      delete c;
+      return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: twiddle upload failed");
+    }
+    const hipError_t me = nlos::mfma_tables_create(device, &c->d_mfma, &c->mt);
+    if (me != hipSuccess) {
+      (void)hipFree(c->d_tw);
+      delete c;
+      return fail(nullptr, me == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
+                  "nlos_create: matrix-core operand tables: %s", hipGetErrorString(me));
+    }
+    const char* mf = std::getenv("NLOS_FK_MFMA");
+    c->mfma = !(mf && mf[0] == '0');
+    *out = c;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: host allocation failed");
   }
-  // W_2048^k = exp(-2 pi i k / 2048) in double with exact octant reduction, stored as float
-  std::vector<float2> tw(nlos::kTwiddleTableN);
-  for (int k = 0; k < nlos::kTwiddleTableN; ++k) {
-    double cs, sn;
-    nlos::cos_sin_2pi_frac(k, nlos::kTwiddleTableN, &cs, &sn);
-    tw[k] = make_float2((float)cs, (float)-sn);
-  }
-  if (hipMalloc(&c->d_tw, tw.size() * sizeof(float2)) != hipSuccess) {
-    delete c;
-    return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_create: twiddle table allocation");
-  }
-  if (hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(c->d_tw);
-    delete c;
-    return fail(nullptr, NLOS_ERR_DEVICE, "nlos_create: twiddle upload failed");
-  }
-  const hipError_t me = nlos::mfma_tables_create(device, &c->d_mfma, &c->mt);
-  if (me != hipSuccess) {
-    (void)hipFree(c->d_tw);
-    delete c;
-    return fail(nullptr, me == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
-                "nlos_create: matrix-core operand tables: %s", hipGetErrorString(me));
-  }
-  const char* mf = std::getenv("NLOS_FK_MFMA");
-  c->mfma = !(mf && mf[0] == '0');
-  *out = c;
-  return NLOS_OK;
 }
 
 nlos_status nlos_destroy(nlos_ctx* ctx) {
@@ -390,7 +425,7 @@ static nlos_status get_workspace(nlos_ctx* ctx, void* d_ws, size_t ws_bytes, siz
     if (ctx->pool) HIP_TRY(ctx, hipFree(ctx->pool));
     ctx->pool = nullptr;
     ctx->pool_bytes = 0;
-    HIP_TRY(ctx, hipMalloc(&ctx->pool, need));
+    HIP_TRY(ctx, nlos::dev_alloc((void**)&ctx->pool, need));
     ctx->pool_bytes = need;
   }
   *out = ctx->pool;
@@ -425,6 +460,23 @@ nlos_status nlos_bin(nlos_ctx* ctx, const nlos_bin_desc* d, const nlos_event* d_
     return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_bin: d_events must be 8-byte aligned");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const size_t nbins = (size_t)d->nx * d->ny * d->nt;
+  const int npix = d->nx * d->ny;
+  const size_t wsb = nlos::bin_workspace_bytes(npix, d->nt, n_events);
+  if (wsb > 0) {
+    // tiled path: its workspace comes from the context pool (stream ordered)
+    void* ws = nullptr;
+    nlos_status st2 = get_workspace(ctx, nullptr, 0, wsb, &ws);
+    if (st2 != NLOS_OK) return st2;
+    if (d_dropped && !d->accumulate)
+      HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] {
+        return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_dropped), 2, 0u, ctx->stream);
+      }));
+    HIP_TRY(ctx, timed(ctx, NLOS_PASS_BIN, [&] {
+      return nlos::launch_bin_tiled(d_events, n_events, d_hist, d_dropped, npix, d->nt, d->bin_ps, d->t0_ps,
+                                    d->accumulate, ws, ctx->stream);
+    }));
+    return NLOS_OK;
+  }
   if (!d->accumulate) {
     HIP_TRY(ctx, timed(ctx, NLOS_PASS_FILL, [&] { return nlos::launch_fill_u32(d_hist, nbins, 0u, ctx->stream); }));
     if (d_dropped)
@@ -472,36 +524,40 @@ nlos_status nlos_phasor_plan_destroy(nlos_phasor_plan* p) {
 
 nlos_status nlos_phasor_plan_create(nlos_ctx* ctx, const nlos_bin_desc* d, int n_freq, const int* freq_bin,
                                     nlos_phasor_plan** out) {
-  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: NULL argument");
-  nlos_status st = nlos_bin_check(d);
-  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
-  if (d->nt > 2048) return fail(ctx, NLOS_ERR_UNSUPPORTED, "phasor_plan_create: nt must be <= 2048");
-  if (n_freq < 1 || !freq_bin) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: need n_freq >= 1 and freq_bin");
-  for (int f = 0; f < n_freq; ++f)
-    if (freq_bin[f] < 0 || freq_bin[f] >= d->nt)
-      return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: freq_bin[%d] = %d outside [0, nt)", f, freq_bin[f]);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  nlos_phasor_plan* p = new (std::nothrow) nlos_phasor_plan();
-  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "phasor_plan_create: host allocation");
-  p->d = *d;
-  p->device = ctx->device;
-  p->nf = n_freq;
-  std::vector<float2> lut(d->nt);
-  for (int m = 0; m < d->nt; ++m) {
-    double c, sn;
-    nlos::cos_sin_2pi_frac(m, d->nt, &c, &sn);
-    lut[m] = make_float2((float)c, (float)-sn);  // exp(-2 pi i m / nt)
+  try {
+    if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: NULL argument");
+    nlos_status st = nlos_bin_check(d);
+    if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+    if (d->nt > 2048) return fail(ctx, NLOS_ERR_UNSUPPORTED, "phasor_plan_create: nt must be <= 2048");
+    if (n_freq < 1 || !freq_bin) return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: need n_freq >= 1 and freq_bin");
+    for (int f = 0; f < n_freq; ++f)
+      if (freq_bin[f] < 0 || freq_bin[f] >= d->nt)
+        return fail(ctx, NLOS_ERR_INVALID_ARG, "phasor_plan_create: freq_bin[%d] = %d outside [0, nt)", f, freq_bin[f]);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    nlos_phasor_plan* p = new (std::nothrow) nlos_phasor_plan();
+    if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "phasor_plan_create: host allocation");
+    p->d = *d;
+    p->device = ctx->device;
+    p->nf = n_freq;
+    std::vector<float2> lut(d->nt);
+    for (int m = 0; m < d->nt; ++m) {
+      double c, sn;
+      nlos::cos_sin_2pi_frac(m, d->nt, &c, &sn);
+      lut[m] = make_float2((float)c, (float)-sn);  // exp(-2 pi i m / nt)
+    }
+    hipError_t e = nlos::dev_alloc((void**)&p->d_lut, lut.size() * sizeof(float2));
+    if (e == hipSuccess) e = nlos::dev_alloc((void**)&p->d_bins, n_freq * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(p->d_lut, lut.data(), lut.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_bins, freq_bin, n_freq * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      nlos_phasor_plan_destroy(p);
+      return fail(ctx, NLOS_ERR_DEVICE, "phasor_plan_create: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "nlos_phasor_plan_create: host allocation failed");
   }
-  hipError_t e = hipMalloc(&p->d_lut, lut.size() * sizeof(float2));
-  if (e == hipSuccess) e = hipMalloc(&p->d_bins, n_freq * sizeof(int));
-  if (e == hipSuccess) e = hipMemcpy(p->d_lut, lut.data(), lut.size() * sizeof(float2), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->d_bins, freq_bin, n_freq * sizeof(int), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    nlos_phasor_plan_destroy(p);
-    return fail(ctx, NLOS_ERR_DEVICE, "phasor_plan_create: %s", hipGetErrorString(e));
-  }
-  *out = p;
-  return NLOS_OK;
 }
 
 nlos_status nlos_phasor_bin(nlos_ctx* ctx, const nlos_phasor_plan* p, const nlos_event* d_events, uint64_t n_events,
@@ -559,7 +615,7 @@ nlos_status nlos_fk_check(const nlos_fk_desc* d) {
   return NLOS_OK;
 }
 
-nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
+nlos_status nlos_fk_desc_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
   nlos_status st = nlos_fk_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "fk: bytes is NULL");
@@ -568,37 +624,48 @@ nlos_status nlos_fk_workspace_bytes(const nlos_fk_desc* d, size_t* bytes) {
 }
 
 nlos_status nlos_fk_plan_create(nlos_ctx* ctx, const nlos_fk_desc* d, nlos_fk_plan** out) {
-  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "fk_plan_create: NULL argument");
-  nlos_status st = nlos_fk_check(d);
-  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
-  nlos_fk_plan* p = new (std::nothrow) nlos_fk_plan();
-  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "fk_plan_create: host allocation");
-  p->d = *d;
-  p->device = ctx->device;
-  p->Mx = d->pad * d->nx;
-  p->My = d->pad * d->ny;
-  p->Mt = d->pad * d->nt;
-  const double c_dt = kC * d->bin_ps * 1e-12;
-  const double sx = c_dt / (2.0 * (d->wall_w_m / d->nx));
-  const double sy = c_dt / (2.0 * (d->wall_h_m / d->ny));
-  p->sxk = sx * (double)p->Mt / (double)p->Mx;
-  p->syk = sy * (double)p->Mt / (double)p->My;
-  p->norm = (float)(1.0 / ((double)p->Mx * (double)p->My * (double)p->Mt));
-  // general axis lengths (the x pass also for odd nt: see gen_xr2c)
-  p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
-  p->gen_y = !is_pow2_in(p->My, 8, 2048);
-  p->gen_t = !is_pow2_in(p->Mt, 8, 2048);
-  p->gen_xr2c = p->gen_x || (d->nt & 1) != 0;
-  const int m[3] = {p->Mx, p->My, p->Mt};
-  const bool use[3] = {p->gen_xr2c, p->gen_y, p->gen_t};
-  nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
-  const hipError_t e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw);
-  if (e != hipSuccess) {
-    delete p;
-    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
-                "fk_plan_create: general-length twiddle tables: %s", hipGetErrorString(e));
+  try {
+    if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "fk_plan_create: NULL argument");
+    nlos_status st = nlos_fk_check(d);
+    if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+    nlos::host_alloc_point();
+    nlos_fk_plan* p = new (std::nothrow) nlos_fk_plan();
+    if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "fk_plan_create: host allocation");
+    p->d = *d;
+    p->device = ctx->device;
+    p->Mx = d->pad * d->nx;
+    p->My = d->pad * d->ny;
+    p->Mt = d->pad * d->nt;
+    const double c_dt = kC * d->bin_ps * 1e-12;
+    const double sx = c_dt / (2.0 * (d->wall_w_m / d->nx));
+    const double sy = c_dt / (2.0 * (d->wall_h_m / d->ny));
+    p->sxk = sx * (double)p->Mt / (double)p->Mx;
+    p->syk = sy * (double)p->Mt / (double)p->My;
+    p->norm = (float)(1.0 / ((double)p->Mx * (double)p->My * (double)p->Mt));
+    // general axis lengths (the x pass also for odd nt: see gen_xr2c)
+    p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
+    p->gen_y = !is_pow2_in(p->My, 8, 2048);
+    p->gen_t = !is_pow2_in(p->Mt, 8, 2048);
+    p->gen_xr2c = p->gen_x || (d->nt & 1) != 0;
+    const int m[3] = {p->Mx, p->My, p->Mt};
+    const bool use[3] = {p->gen_xr2c, p->gen_y, p->gen_t};
+    nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
+    const hipError_t e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE,
+                  "fk_plan_create: general-length twiddle tables: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "nlos_fk_plan_create: host allocation failed");
   }
-  *out = p;
+}
+
+nlos_status nlos_fk_workspace_bytes(const nlos_fk_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_fk_workspace_bytes: NULL argument");
+  *bytes = fk_layout(&p->d).bytes;
   return NLOS_OK;
 }
 
@@ -742,7 +809,7 @@ nlos_status nlos_fk(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d_tau, fl
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk: plan of another device");
   const nlos_fk_desc& d = p->d;
   size_t need = 0;
-  nlos_status st = nlos_fk_workspace_bytes(&d, &need);
+  nlos_status st = nlos_fk_desc_workspace_bytes(&d, &need);
   if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
@@ -759,7 +826,7 @@ nlos_status nlos_fk_noalloc(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_noalloc: plan of another device");
   size_t need = 0;
-  nlos_status st = nlos_fk_workspace_bytes(&p->d, &need);
+  nlos_status st = nlos_fk_desc_workspace_bytes(&p->d, &need);
   if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
   if (need > nlos::kStaticScratchBytes)
     return fail(ctx, NLOS_ERR_UNSUPPORTED,
@@ -833,6 +900,8 @@ nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
     return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: depth grid must be finite");
   if (d->sigma_s != 1 && d->sigma_s != 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: sigma_s must be 1 or 2");
   if (d->sigma_t < 0 || d->sigma_t > 2) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: sigma_t must be 0, 1 or 2");
+  if (d->vol_depth_major != 0 && d->vol_depth_major != 1)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: vol_depth_major must be 0 or 1");
   if (d->data_prec < NLOS_FP32 || d->data_prec > NLOS_BF16 || d->kernel_prec < NLOS_FP32 ||
       d->kernel_prec > NLOS_BF16)
     return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bad precision");
@@ -855,39 +924,54 @@ nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
 }
 
 nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc* d, nlos_rsd_geometry* out) {
-  nlos_status st = nlos_rsd_check(d);
-  if (st != NLOS_OK) return st;
-  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_geometry_get: out is NULL");
-  const nlos::RsdGeometry g = nlos::rsd_geometry(rsd_inputs(d));
-  out->r_max = g.r_max; out->rho_max = g.rho_max; out->lambda_min = g.lambda_min; out->dr = g.dr;
-  out->f_s = g.f_s; out->rho_cut = g.rho_cut; out->rho_cut_bin = g.rho_cut_bin;
-  out->n_r_min = g.n_r_min; out->n_r = g.n_r; out->n_rho_min = g.n_rho_min; out->n_rho = g.n_rho;
-  out->cut_idx = g.cut_idx; out->last_base = g.last_base;
-  return NLOS_OK;
+  try {
+    nlos_status st = nlos_rsd_check(d);
+    if (st != NLOS_OK) return st;
+    if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_geometry_get: out is NULL");
+    const nlos::RsdGeometry g = nlos::rsd_geometry(rsd_inputs(d));
+    out->r_max = g.r_max; out->rho_max = g.rho_max; out->lambda_min = g.lambda_min; out->dr = g.dr;
+    out->f_s = g.f_s; out->rho_cut = g.rho_cut; out->rho_cut_bin = g.rho_cut_bin;
+    out->n_r_min = g.n_r_min; out->n_r = g.n_r; out->n_rho_min = g.n_rho_min; out->n_rho = g.n_rho;
+    out->cut_idx = g.cut_idx; out->last_base = g.last_base;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_rsd_geometry_get: host allocation failed");
+  }
 }
 
 nlos_status nlos_rsd_kernel_host(const nlos_rsd_desc* d, float* out, size_t n_floats) {
-  nlos_status st = nlos_rsd_check(d);
-  if (st != NLOS_OK) return st;
-  if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: out is NULL");
-  const nlos::RsdInputs in = rsd_inputs(d);
-  const nlos::RsdGeometry g = nlos::rsd_geometry(in);
-  const size_t need = 2ull * g.n_rho * d->n_freq * d->n_depth;
-  if (n_floats < need) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: need %zu floats", need);
-  std::vector<double> re, im;
-  nlos::rsd_radial_kernel(in, g, re, im);
-  for (size_t i = 0; i < re.size(); ++i) {
-    out[2 * i] = (float)re[i];
-    out[2 * i + 1] = (float)im[i];
+  try {
+    nlos_status st = nlos_rsd_check(d);
+    if (st != NLOS_OK) return st;
+    if (!out) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: out is NULL");
+    const nlos::RsdInputs in = rsd_inputs(d);
+    const nlos::RsdGeometry g = nlos::rsd_geometry(in);
+    const size_t need = 2ull * g.n_rho * d->n_freq * d->n_depth;
+    nlos::host_alloc_point();
+    if (n_floats < need) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd_kernel_host: need %zu floats", need);
+    std::vector<double> re, im;
+    nlos::rsd_radial_kernel(in, g, re, im);
+    for (size_t i = 0; i < re.size(); ++i) {
+      out[2 * i] = (float)re[i];
+      out[2 * i + 1] = (float)im[i];
+    }
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, NLOS_ERR_OUT_OF_MEMORY, "nlos_rsd_kernel_host: host allocation failed");
   }
-  return NLOS_OK;
 }
 
-nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_desc* d, size_t* bytes) {
+nlos_status nlos_rsd_desc_workspace_bytes(const nlos_rsd_desc* d, size_t* bytes) {
   nlos_status st = nlos_rsd_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bytes is NULL");
   *bytes = rsd_layout(d).total * 8;
+  return NLOS_OK;
+}
+
+nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_rsd_workspace_bytes: NULL argument");
+  *bytes = rsd_layout(&p->d).total * 8;
   return NLOS_OK;
 }
 
@@ -907,78 +991,85 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan* p) {
 }
 
 nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd_plan** out) {
-  if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "rsd_plan_create: NULL argument");
-  nlos_status st = nlos_rsd_check(d);
-  if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  nlos_rsd_plan* p = new (std::nothrow) nlos_rsd_plan();
-  if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "rsd_plan_create: host allocation");
-  p->d = *d;
-  p->d.freq_bin = nullptr;  // host arrays are copied to the device below
-  p->d.w = nullptr;
-  p->device = ctx->device;
-  p->Mx = d->pad * d->nx;
-  p->My = d->pad * d->ny;
-  const nlos::RsdInputs in = rsd_inputs(d);
-  p->g = nlos::rsd_geometry(in);
-  std::vector<double> kre, kim;
-  nlos::rsd_radial_kernel(in, p->g, kre, kim);
-  nlos::RsdChunks ch;
-  nlos::rsd_build_chunks(in, p->g, ch);
-  const size_t nk = kre.size();
-  auto cleanup = [&](nlos_status s, const char* what, hipError_t e) {
-    nlos_rsd_plan_destroy(p);
-    return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : s, "rsd_plan_create: %s: %s", what,
-                hipGetErrorString(e));
-  };
-  hipError_t e;
-  if (d->kernel_prec == NLOS_FP16) {
-    // FP64 accumulation, a single rounding to binary16 on store
-    std::vector<_Float16> kh(2 * nk);
-    for (size_t i = 0; i < nk; ++i) {
-      kh[2 * i] = (_Float16)kre[i];
-      kh[2 * i + 1] = (_Float16)kim[i];
+  nlos_rsd_plan* p = nullptr;
+  try {
+    if (!ctx || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "rsd_plan_create: NULL argument");
+    nlos_status st = nlos_rsd_check(d);
+    if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    nlos::host_alloc_point();
+    p = new (std::nothrow) nlos_rsd_plan();
+    if (!p) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "rsd_plan_create: host allocation");
+    p->d = *d;
+    p->d.freq_bin = nullptr;  // host arrays are copied to the device below
+    p->d.w = nullptr;
+    p->device = ctx->device;
+    p->Mx = d->pad * d->nx;
+    p->My = d->pad * d->ny;
+    const nlos::RsdInputs in = rsd_inputs(d);
+    p->g = nlos::rsd_geometry(in);
+    std::vector<double> kre, kim;
+    nlos::rsd_radial_kernel(in, p->g, kre, kim);
+    nlos::RsdChunks ch;
+    nlos::rsd_build_chunks(in, p->g, ch);
+    const size_t nk = kre.size();
+    auto cleanup = [&](nlos_status s, const char* what, hipError_t e) {
+      nlos_rsd_plan_destroy(p);
+      return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : s, "rsd_plan_create: %s: %s", what,
+                  hipGetErrorString(e));
+    };
+    hipError_t e;
+    if (d->kernel_prec == NLOS_FP16) {
+      // FP64 accumulation, a single rounding to binary16 on store
+      std::vector<_Float16> kh(2 * nk);
+      for (size_t i = 0; i < nk; ++i) {
+        kh[2 * i] = (_Float16)kre[i];
+        kh[2 * i + 1] = (_Float16)kim[i];
+      }
+      if ((e = nlos::dev_alloc((void**)&p->d_kr, nk * 4)) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
+      if ((e = hipMemcpy(p->d_kr, kh.data(), nk * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
+    } else {
+      std::vector<float2> kf(nk);
+      for (size_t i = 0; i < nk; ++i) kf[i] = make_float2((float)kre[i], (float)kim[i]);
+      if ((e = nlos::dev_alloc((void**)&p->d_kr, nk * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
+      if ((e = hipMemcpy(p->d_kr, kf.data(), nk * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
     }
-    if ((e = hipMalloc(&p->d_kr, nk * 4)) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
-    if ((e = hipMemcpy(p->d_kr, kh.data(), nk * 4, hipMemcpyHostToDevice)) != hipSuccess)
-      return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
-  } else {
-    std::vector<float2> kf(nk);
-    for (size_t i = 0; i < nk; ++i) kf[i] = make_float2((float)kre[i], (float)kim[i]);
-    if ((e = hipMalloc(&p->d_kr, nk * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
-    if ((e = hipMemcpy(p->d_kr, kf.data(), nk * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
-      return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
+    p->nchunks = ch.count();
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+      hipError_t r = nlos::dev_alloc((void**)dst, bytes);
+      if (r == hipSuccess) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+      return r;
+    };
+    if ((e = upload((void**)&p->d_chunk_i0, ch.i0.data(), ch.i0.size() * sizeof(int))) != hipSuccess ||
+        (e = upload((void**)&p->d_chunk_pix, ch.pix.data(), ch.pix.size() * sizeof(int))) != hipSuccess ||
+        (e = upload((void**)&p->d_chunk_wa, ch.wa.data(), ch.wa.size() * sizeof(float))) != hipSuccess ||
+        (e = upload((void**)&p->d_chunk_wb, ch.wb.data(), ch.wb.size() * sizeof(float))) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "pixel chunks", e);
+    std::vector<float2> w(d->n_freq);
+    for (int f = 0; f < d->n_freq; ++f) w[f] = make_float2(d->w[2 * f], d->w[2 * f + 1]);
+    if ((e = nlos::dev_alloc((void**)&p->d_w, w.size() * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "w", e);
+    if ((e = hipMemcpy(p->d_w, w.data(), w.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "w upload", e);
+    std::vector<int> bins(d->freq_bin, d->freq_bin + d->n_freq);
+    if ((e = nlos::dev_alloc((void**)&p->d_bins, bins.size() * sizeof(int))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "bins", e);
+    if ((e = hipMemcpy(p->d_bins, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "bins upload", e);
+    p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
+    p->gen_y = !is_pow2_in(p->My, 8, 2048);
+    p->gen_t = !is_pow2_in(d->nt, 8, 2048);
+    const int m[3] = {p->Mx, p->My, d->nt};
+    const bool use[3] = {p->gen_x, p->gen_y, p->gen_t};
+    nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
+    if ((e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw)) != hipSuccess)
+      return cleanup(NLOS_ERR_DEVICE, "general-length twiddle tables", e);
+    *out = p;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    nlos_rsd_plan_destroy(p);
+    return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "nlos_rsd_plan_create: host allocation failed");
   }
-  p->nchunks = ch.count();
-  auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(dst, bytes);
-    if (r == hipSuccess) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-    return r;
-  };
-  if ((e = upload((void**)&p->d_chunk_i0, ch.i0.data(), ch.i0.size() * sizeof(int))) != hipSuccess ||
-      (e = upload((void**)&p->d_chunk_pix, ch.pix.data(), ch.pix.size() * sizeof(int))) != hipSuccess ||
-      (e = upload((void**)&p->d_chunk_wa, ch.wa.data(), ch.wa.size() * sizeof(float))) != hipSuccess ||
-      (e = upload((void**)&p->d_chunk_wb, ch.wb.data(), ch.wb.size() * sizeof(float))) != hipSuccess)
-    return cleanup(NLOS_ERR_DEVICE, "pixel chunks", e);
-  std::vector<float2> w(d->n_freq);
-  for (int f = 0; f < d->n_freq; ++f) w[f] = make_float2(d->w[2 * f], d->w[2 * f + 1]);
-  if ((e = hipMalloc(&p->d_w, w.size() * sizeof(float2))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "w", e);
-  if ((e = hipMemcpy(p->d_w, w.data(), w.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(NLOS_ERR_DEVICE, "w upload", e);
-  std::vector<int> bins(d->freq_bin, d->freq_bin + d->n_freq);
-  if ((e = hipMalloc(&p->d_bins, bins.size() * sizeof(int))) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "bins", e);
-  if ((e = hipMemcpy(p->d_bins, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(NLOS_ERR_DEVICE, "bins upload", e);
-  p->gen_x = !is_pow2_in(p->Mx, 8, 2048);
-  p->gen_y = !is_pow2_in(p->My, 8, 2048);
-  p->gen_t = !is_pow2_in(d->nt, 8, 2048);
-  const int m[3] = {p->Mx, p->My, d->nt};
-  const bool use[3] = {p->gen_x, p->gen_y, p->gen_t};
-  nlos::GenPlan* const g[3] = {&p->gx, &p->gy, &p->gt};
-  if ((e = gen_tables(ctx->device, m, use, g, 3, &p->d_gtw)) != hipSuccess)
-    return cleanup(NLOS_ERR_DEVICE, "general-length twiddle tables", e);
-  *out = p;
-  return NLOS_OK;
 }
 
 // The RSD pass sequence on stream s with workspace ws (validated by the caller).
@@ -1058,10 +1149,19 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
     }));
     return NLOS_OK;
   }
+  // depth-major volume: |I| lands depth contiguous in region B (C is dead), then one
+  // transpose pass writes d_vol[n_depth][ny][nx]
+  const bool depth_major = d.vol_depth_major && d_vol != nullptr;
+  float* vtmp = reinterpret_cast<float*>(base + L.b_off);
+  if (depth_major) a.out = vtmp;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] {
     return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_ABS_IMG, a, (int)ny, s)
                     : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s);
   }));
+  if (depth_major)
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
+      return nlos::launch_transpose_f32(vtmp, d_vol, ny * nx, (int)Nd, s);
+    }));
   return NLOS_OK;
 }
 
@@ -1186,7 +1286,7 @@ nlos_status nlos_fk_graph_create(nlos_ctx* ctx, const nlos_fk_plan* p, const flo
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_fk_graph_create: plan of another device");
   size_t need = 0;
-  nlos_status st = nlos_fk_workspace_bytes(&p->d, &need);
+  nlos_status st = nlos_fk_desc_workspace_bytes(&p->d, &need);
   if (st != NLOS_OK) return fail(ctx, st, "%s", g_err.c_str());
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
@@ -1250,7 +1350,7 @@ nlos_status nlos_merge_create(nlos_ctx* ctx, uint64_t n_values, int window, doub
   m->n = (long long)n_values;
   m->window = window;
   m->eps = (float)eps;
-  hipError_t e = hipMalloc(&m->ring, (size_t)window * n_values * sizeof(float2));
+  hipError_t e = nlos::dev_alloc((void**)&m->ring, (size_t)window * n_values * sizeof(float2));
   if (e != hipSuccess) {
     delete m;
     return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE, "merge_create: %s",

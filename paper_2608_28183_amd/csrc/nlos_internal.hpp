@@ -180,16 +180,31 @@ hipError_t launch_fk_column_pair_mfma(const FkPairArgs& a, const MfmaTables& t, 
 bool mfma_zfft_ok(int mt, int sp, const ContigArgs& a);
 hipError_t launch_zfft_abs2_mfma(const ContigArgs& a, const MfmaTables& t, const float2* tw, hipStream_t s, int sp);
 
+// Every device allocation of the library goes through dev_alloc and every host allocation
+// point calls host_alloc_point (it throws std::bad_alloc, caught at the C boundary), so
+// that nlos_debug_fail_allocations can make the next allocations fail.
+hipError_t dev_alloc(void** p, size_t bytes);
+void host_alloc_point();
+
 // Static device scratch of the allocation-free entry points (k_scratch.hip): its size,
 // and its device address on `device` (looked up once per device with that device
 // current, then cached; the array's name itself is never passed to a kernel).
 constexpr size_t kStaticScratchBytes = size_t(128) << 20;
 hipError_t static_scratch_address(int device, void** out);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t value, hipStream_t s);
+// out[c][r] = in[r][c] for r < rows, c < cols (float)
+hipError_t launch_transpose_f32(const float* in, float* out, long long rows, int cols, hipStream_t s);
 hipError_t launch_u32_to_f32(const uint32_t* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_bin(const void* events, unsigned long long n, uint32_t* hist,
                       unsigned long long* dropped, int npix, int nt, uint32_t bin_ps, uint32_t t0,
                       hipStream_t s);
+// Binning by pixel tiles (each chunk sorted by tile into runs, then one LDS histogram per
+// tile gathered from every chunk's run) into workspace ws of
+// bin_workspace_bytes (0: the tiled path does not apply to this shape); every bin of hist is
+// written (added to when accumulate), so no clearing pass is needed.
+size_t bin_workspace_bytes(int npix, int nt, unsigned long long n);
+hipError_t launch_bin_tiled(const void* events, unsigned long long n, uint32_t* hist, unsigned long long* dropped,
+                            int npix, int nt, uint32_t bin_ps, uint32_t t0, int accumulate, void* ws, hipStream_t s);
 // P[pixel][f] += W_nt^(bins[f] b) per valid event (nt <= 2048, lut = W_nt^m, m < nt)
 hipError_t launch_phasor_bin(const void* events, unsigned long long n, float2* P, unsigned long long* dropped,
                              int npix, int nt, uint32_t bin_ps, uint32_t t0, const float2* lut, const int* bins,

@@ -12,7 +12,8 @@ import os
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnlos.so")
+# NLOS_LIBRARY selects another build of the same library (the host-sanitizer build in tests)
+LIB_PATH = os.environ.get("NLOS_LIBRARY") or os.path.join(_HERE, "libnlos.so")
 
 NLOS_OK = 0
 NLOS_ERR_INVALID_ARG = 1
@@ -57,7 +58,8 @@ class nlos_rsd_desc(ctypes.Structure):
                 ("n_depth", ctypes.c_int), ("depth0_m", ctypes.c_double),
                 ("depth_step_m", ctypes.c_double), ("sigma_s", ctypes.c_int),
                 ("sigma_t", ctypes.c_int), ("delta_m", ctypes.c_double),
-                ("data_prec", ctypes.c_int), ("kernel_prec", ctypes.c_int)]
+                ("data_prec", ctypes.c_int), ("kernel_prec", ctypes.c_int),
+                ("vol_depth_major", ctypes.c_int)]
 
 
 class nlos_rsd_geometry(ctypes.Structure):
@@ -85,7 +87,8 @@ _SIGNATURES = {
     "nlos_bin": (_ST, [_VP, ctypes.POINTER(nlos_bin_desc), _VP, ctypes.c_uint64, _VP, _VP]),
     "nlos_counts_to_float": (_ST, [_VP, _VP, _VP, ctypes.c_uint64]),
     "nlos_fk_check": (_ST, [ctypes.POINTER(nlos_fk_desc)]),
-    "nlos_fk_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_fk_desc_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_fk_workspace_bytes": (_ST, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "nlos_fk_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(_VP)]),
     "nlos_fk_plan_destroy": (_ST, [_VP]),
     "nlos_fk": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
@@ -94,7 +97,8 @@ _SIGNATURES = {
     "nlos_rsd_geometry_get": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(nlos_rsd_geometry)]),
     "nlos_rsd_kernel_host": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_float),
                                    ctypes.c_size_t]),
-    "nlos_rsd_workspace_bytes": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_rsd_desc_workspace_bytes": (_ST, [ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "nlos_rsd_workspace_bytes": (_ST, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "nlos_rsd_plan_create": (_ST, [_VP, ctypes.POINTER(nlos_rsd_desc), ctypes.POINTER(_VP)]),
     "nlos_rsd_plan_destroy": (_ST, [_VP]),
     "nlos_rsd": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t]),
@@ -121,6 +125,7 @@ _SIGNATURES = {
     "nlos_rsd_graph_create": (_ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
     "nlos_graph_launch": (_ST, [_VP, _VP]),
     "nlos_graph_destroy": (_ST, [_VP]),
+    "nlos_debug_fail_allocations": (None, [ctypes.c_int]),
 }
 
 _lib = None
@@ -167,6 +172,11 @@ def _stream_handle(stream) -> Optional[int]:
 # ---------------------------------------------------------------------------
 # context
 # ---------------------------------------------------------------------------
+
+def nlos_debug_fail_allocations(n: int) -> None:
+    """Test hook (include/nlos_debug.h): the next n allocations of the library fail."""
+    lib().nlos_debug_fail_allocations(n)
+
 
 def nlos_version() -> int:
     return lib().nlos_version()
@@ -253,10 +263,16 @@ def nlos_fk_check(desc: nlos_fk_desc) -> int:
     return lib().nlos_fk_check(ctypes.byref(desc))
 
 
-def nlos_fk_workspace_bytes(desc: nlos_fk_desc) -> int:
-    out = ctypes.c_size_t()
-    _check(lib().nlos_fk_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)),
-           "nlos_fk_workspace_bytes")
+def nlos_fk_desc_workspace_bytes(desc: nlos_fk_desc) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().nlos_fk_desc_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)),
+           "nlos_fk_desc_workspace_bytes")
+    return out.value
+
+
+def nlos_fk_workspace_bytes(plan: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().nlos_fk_workspace_bytes(plan, ctypes.byref(out)), "nlos_fk_workspace_bytes")
     return out.value
 
 
@@ -293,7 +309,7 @@ class RsdDesc:
 
     def __init__(self, nx, ny, nt, dx_m, dy_m, bin_ps, pad, freq_bins: Sequence[int], weights,
                  n_depth, depth0_m, depth_step_m, sigma_s=2, sigma_t=0, delta_m=0.0,
-                 data_prec="fp32", kernel_prec="fp32"):
+                 data_prec="fp32", kernel_prec="fp32", vol_depth_major=False):
         n = len(freq_bins)
         self._bins = (ctypes.c_int32 * n)(*[int(k) for k in freq_bins])
         wf = []
@@ -304,7 +320,7 @@ class RsdDesc:
                                ctypes.cast(self._bins, ctypes.POINTER(ctypes.c_int32)),
                                ctypes.cast(self._w, ctypes.POINTER(ctypes.c_float)),
                                n_depth, depth0_m, depth_step_m, sigma_s, sigma_t, delta_m,
-                               PRECISIONS[data_prec], PRECISIONS[kernel_prec])
+                               PRECISIONS[data_prec], PRECISIONS[kernel_prec], int(bool(vol_depth_major)))
 
 
 def nlos_rsd_check(desc: RsdDesc) -> int:
@@ -329,10 +345,16 @@ def nlos_rsd_kernel_host(desc: RsdDesc):
     return out.view(np.complex64).reshape(g["n_rho"], desc.c.n_freq, desc.c.n_depth)
 
 
-def nlos_rsd_workspace_bytes(desc: RsdDesc) -> int:
-    out = ctypes.c_size_t()
-    _check(lib().nlos_rsd_workspace_bytes(ctypes.byref(desc.c), ctypes.byref(out)),
-           "nlos_rsd_workspace_bytes")
+def nlos_rsd_desc_workspace_bytes(desc: RsdDesc) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().nlos_rsd_desc_workspace_bytes(ctypes.byref(desc.c), ctypes.byref(out)),
+           "nlos_rsd_desc_workspace_bytes")
+    return out.value
+
+
+def nlos_rsd_workspace_bytes(plan: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().nlos_rsd_workspace_bytes(plan, ctypes.byref(out)), "nlos_rsd_workspace_bytes")
     return out.value
 
 

@@ -65,8 +65,8 @@ class FkPlan:
         self.ctx = ctx
         self.shape = (ny, nx, nt)
         self.desc = nlos.fk_desc(nx, ny, nt, wall_w, wall_h, bin_ps, pad, prec)
-        self.ws_bytes = nlos.nlos_fk_workspace_bytes(self.desc)
         self.handle = nlos.nlos_fk_plan_create(ctx.handle, self.desc)
+        self.ws_bytes = nlos.nlos_fk_workspace_bytes(self.handle)
 
     def workspace(self) -> torch.Tensor:
         return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
@@ -94,24 +94,27 @@ class RsdPlan:
     def __init__(self, ctx: Context, ny: int, nx: int, nt: int, dx: float, dy: float, bin_ps: float,
                  pad: int, freq_bins, weights, n_depth: int, depth0: float, depth_step: float,
                  sigma_s: int = 2, sigma_t: int = 0, delta: float = 0.0, data_prec: str = "fp32",
-                 kernel_prec: str = "fp32"):
+                 kernel_prec: str = "fp32", vol_depth_major: bool = False):
         self.ctx = ctx
         self.shape = (ny, nx, nt)
         self.n_depth = n_depth
+        self.depth_major = bool(vol_depth_major)
         self.desc = nlos.RsdDesc(nx, ny, nt, dx, dy, bin_ps, pad, freq_bins, weights, n_depth,
                                  depth0, depth_step, sigma_s, sigma_t, delta, data_prec,
-                                 kernel_prec)
-        self.ws_bytes = nlos.nlos_rsd_workspace_bytes(self.desc)
+                                 kernel_prec, vol_depth_major)
         self.handle = nlos.nlos_rsd_plan_create(ctx.handle, self.desc)
+        self.ws_bytes = nlos.nlos_rsd_workspace_bytes(self.handle)
 
     def workspace(self) -> torch.Tensor:
         return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
 
     def __call__(self, tau: torch.Tensor, vol=None, img=None, ws=None):
-        """vol: float32 [ny, nx, n_depth] (depth contiguous); img: float32 [ny, nx]."""
+        """vol: float32 [ny, nx, n_depth] (depth contiguous) or, for a depth-major plan,
+        [n_depth, ny, nx]; img: float32 [ny, nx]."""
         ny, nx, nt = self.shape
         assert tau.shape == (ny, nx, nt) and tau.dtype == torch.float32 and tau.is_cuda
-        assert vol is None or vol.shape == (ny, nx, self.n_depth)
+        want = (self.n_depth, ny, nx) if self.depth_major else (ny, nx, self.n_depth)
+        assert vol is None or vol.shape == want
         nlos.nlos_rsd(self.ctx.handle, self.handle, tau, vol, img, ws)
         return vol, img
 

@@ -15,9 +15,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "nlos.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nlos_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(nlos_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -68,12 +72,12 @@ def fk_ws_expected(ny, nx, nt, pad, es=8):
 
 def test_fk_workspace_is_exact():
     d = nlos.fk_desc(256, 256, 512, 1.0, 1.0, 32.0, pad=2)
-    assert nlos.nlos_fk_workspace_bytes(d) == fk_ws_expected(256, 256, 512, 2)
-    assert nlos.nlos_fk_workspace_bytes(d) < 1.9e9
+    assert nlos.nlos_fk_desc_workspace_bytes(d) == fk_ws_expected(256, 256, 512, 2)
+    assert nlos.nlos_fk_desc_workspace_bytes(d) < 1.9e9
     d = nlos.fk_desc(32, 16, 64, 1.0, 1.0, 32.0, pad=1)
-    assert nlos.nlos_fk_workspace_bytes(d) == fk_ws_expected(16, 32, 64, 1)
+    assert nlos.nlos_fk_desc_workspace_bytes(d) == fk_ws_expected(16, 32, 64, 1)
     with pytest.raises(nlos.NlosError):
-        nlos.nlos_fk_workspace_bytes(nlos.fk_desc(3, 8, 8, 1.0, 1.0, 32.0))
+        nlos.nlos_fk_desc_workspace_bytes(nlos.fk_desc(3, 8, 8, 1.0, 1.0, 32.0))
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -85,10 +89,10 @@ def test_fk_reduced_workspace(prec, shape):
     d = nlos.fk_desc(nx, ny, nt, 1.0, 1.0, 32.0, pad=pad, prec=prec)
     data = fk_ws_expected(ny, nx, nt, pad, es=4)
     want = data if prec == "bf16" else (data + 255) // 256 * 256 + 4 * 1024 + 256
-    assert nlos.nlos_fk_workspace_bytes(d) == want
+    assert nlos.nlos_fk_desc_workspace_bytes(d) == want
     if shape[0] == 256:
-        full = nlos.nlos_fk_workspace_bytes(nlos.fk_desc(nx, ny, nt, 1.0, 1.0, 32.0, pad=pad))
-        assert nlos.nlos_fk_workspace_bytes(d) < 0.51 * full
+        full = nlos.nlos_fk_desc_workspace_bytes(nlos.fk_desc(nx, ny, nt, 1.0, 1.0, 32.0, pad=pad))
+        assert nlos.nlos_fk_desc_workspace_bytes(d) < 0.51 * full
 
 
 def test_bin_validation():
@@ -205,6 +209,94 @@ def test_moe_validation_and_workspace():
     assert nlos.nlos_moe_check(fd, rd, beta=-0.1) == nlos.NLOS_ERR_INVALID_ARG
     assert nlos.nlos_moe_check(fd, rd, eps=0.0) == nlos.NLOS_ERR_INVALID_ARG
     up = lambda b: (b + 255) // 256 * 256  # noqa: E731
-    want = up(nlos.nlos_fk_workspace_bytes(fd)) + up(nlos.nlos_rsd_workspace_bytes(rd)) + 256 + \
+    want = up(nlos.nlos_fk_desc_workspace_bytes(fd)) + up(nlos.nlos_rsd_desc_workspace_bytes(rd)) + 256 + \
         up(2 * 4 * cfg.nx * cfg.ny)
     assert nlos.nlos_moe_workspace_bytes(fd, rd) == want
+
+
+# The boundary: the entry points a caller of binning, f-k and RSD needs, with their
+# parameter types.  nlos_fk / nlos_rsd take the caller's workspace size after the
+# workspace pointer, so that a short workspace is refused before any launch.
+BOUNDARY = {
+    "nlos_create": ["int", "void *", "nlos_ctx **"],
+    "nlos_destroy": ["nlos_ctx *"],
+    "nlos_set_stream": ["nlos_ctx *", "void *"],
+    "nlos_status_string": ["nlos_status"],
+    "nlos_last_error": ["const nlos_ctx *"],
+    "nlos_bin": ["nlos_ctx *", "const nlos_bin_desc *", "const nlos_event *", "uint64_t", "uint32_t *",
+                 "unsigned long long *"],
+    "nlos_fk_plan_create": ["nlos_ctx *", "const nlos_fk_desc *", "nlos_fk_plan **"],
+    "nlos_fk_plan_destroy": ["nlos_fk_plan *"],
+    "nlos_fk_workspace_bytes": ["const nlos_fk_plan *", "size_t *"],
+    "nlos_fk": ["nlos_ctx *", "const nlos_fk_plan *", "const float *", "float *", "float *", "void *", "size_t"],
+    "nlos_rsd_plan_create": ["nlos_ctx *", "const nlos_rsd_desc *", "nlos_rsd_plan **"],
+    "nlos_rsd_plan_destroy": ["nlos_rsd_plan *"],
+    "nlos_rsd_workspace_bytes": ["const nlos_rsd_plan *", "size_t *"],
+    "nlos_rsd": ["nlos_ctx *", "const nlos_rsd_plan *", "const float *", "float *", "float *", "void *", "size_t"],
+}
+
+
+def declared_signatures():
+    text = open(os.path.join(ROOT, "include", "nlos.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b[\w ]+?\*?\s*\b(nlos_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", text):
+        params = []
+        for p in m.group(2).split(","):
+            p = " ".join(p.replace("*", " * ").split())
+            toks = p.split(" ")
+            if toks and toks[-1] not in ("*",) and len(toks) > 1 and toks[-1] not in ("void",):
+                toks = toks[:-1]  # the parameter's name
+            params.append(" ".join(toks).replace("* *", "**"))
+        out[m.group(1)] = params
+    return out
+
+
+def test_boundary_signatures():
+    sig = declared_signatures()
+    for name, want in BOUNDARY.items():
+        assert name in sig, name
+        assert sig[name] == want, (name, sig[name], want)
+    lib = nlos.lib()
+    for name in BOUNDARY:
+        assert hasattr(lib, name)
+
+
+def test_boundary_descriptors():
+    assert [f for f, _ in nlos.nlos_fk_desc._fields_] == ["nx", "ny", "nt", "wall_w_m", "wall_h_m", "bin_ps",
+                                                          "pad", "prec"]
+    assert [f for f, _ in nlos.nlos_bin_desc._fields_] == ["nx", "ny", "nt", "bin_ps", "t0_ps", "accumulate"]
+    assert [f for f, _ in nlos.nlos_rsd_desc._fields_] == [
+        "nx", "ny", "nt", "dx_m", "dy_m", "bin_ps", "pad", "n_freq", "freq_bin", "w", "n_depth", "depth0_m",
+        "depth_step_m", "sigma_s", "sigma_t", "delta_m", "data_prec", "kernel_prec", "vol_depth_major"]
+    text = open(os.path.join(ROOT, "include", "nlos.h")).read()
+    for f in ("int vol_depth_major;", "nlos_precision data_prec;", "nlos_precision prec;"):
+        assert f in text
+
+
+def test_rsd_layout_flag_validated():
+    cfg = scenes.CONFIGS["c1"]
+    d = nlos.RsdDesc(32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01, vol_depth_major=True)
+    assert nlos.nlos_rsd_check(d) == nlos.NLOS_OK
+    d.c.vol_depth_major = 2
+    assert nlos.nlos_rsd_check(d) == nlos.NLOS_ERR_INVALID_ARG
+
+
+def test_injected_host_allocation_failure_leaves_the_library_usable():
+    """A failing host allocation returns NLOS_ERR_OUT_OF_MEMORY (no exception crosses the C
+    boundary); the next call, with memory available again, succeeds with the same result."""
+    cfg = scenes.CONFIGS["c1"]
+    p = scenes.rsd_params(cfg, 8)
+    d = nlos.RsdDesc(cfg.nx, cfg.ny, cfg.nt, cfg.dx, cfg.dy, cfg.bin_ps, 2, p.freq_bins, p.weights, p.n_depth,
+                     p.depth0, p.depth_step)
+    ref = nlos.nlos_rsd_kernel_host(d)
+    nlos.nlos_debug_fail_allocations(1)
+    try:
+        with pytest.raises(nlos.NlosError) as e:
+            nlos.nlos_rsd_kernel_host(d)
+        assert e.value.status == nlos.NLOS_ERR_OUT_OF_MEMORY
+        assert "allocation" in nlos.nlos_last_error(None)
+    finally:
+        nlos.nlos_debug_fail_allocations(0)
+    again = nlos.nlos_rsd_kernel_host(d)
+    assert np.array_equal(again, ref)

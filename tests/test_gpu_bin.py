@@ -73,3 +73,29 @@ def test_bin_hot_bin_aggregation(ctx):
     ev["t_ps"] = 33
     h, d = gpu_bin(ctx, ev, 4, 4, 8, 10)
     assert h[1, 1, 3] == 300001 and h.sum() == 300001 and d == 0
+
+
+# (nx, ny, nt, bin_ps, n events, invalid fraction, t0): the tile layouts of the tiled path
+# (tp = 8192 // nt pixels per tile) and the per-event path beyond it
+LAYOUTS = [
+    (128, 128, 1024, 3, 3_000_000, 0.05, 0),        # 2048 tiles of 8 pixels
+    (256, 256, 512, 7, 1_000_000, 0.02, 0),         # 4096 tiles of 16 pixels, sparse runs
+    (91, 90, 8192, 1, 400_000, 0.01, 0),            # 8190 tiles of one pixel
+    (40, 30, 700, 4093, 2_000_000, 0.1, 12345),     # ragged last tile, odd bin width, t0
+    (32, 32, 256, 5, 16_789_505, 0.01, 0),          # more than 2048 chunks: two gather rounds
+    (8, 8, 64, 1, 100_000, 0.0, 0),                 # unit bin width
+    (8, 8, 3, 1_431_655_765, 200_000, 0.0, 0),      # times over the whole u32 range
+    (4, 4, 1, 2 ** 31 + 1, 50_000, 0.0, 0),         # bin width above 2^31
+    (16, 16, 9000, 3, 500_000, 0.05, 0),            # nt > 8192: per-event atomic path
+]
+
+
+@pytest.mark.parametrize("nx,ny,nt,bin_ps,n,inval,t0", LAYOUTS)
+def test_bin_tile_layouts(ctx, nx, ny, nt, bin_ps, n, inval, t0):
+    say(f"bin layout {nx}x{ny}x{nt} bin_ps={bin_ps} n={n} invalid={inval} t0={t0}")
+    ev = scenes.random_events(n, nx, ny, nt, bin_ps, seed=nx * 7 + nt, invalid_frac=inval)
+    if t0:
+        ev["t_ps"] = ev["t_ps"] + np.uint32(t0)
+    h, d = gpu_bin(ctx, ev, nx, ny, nt, bin_ps, t0)
+    ref, rd = binning.bin_events(ev["pixel"], ev["t_ps"], nx, ny, nt, bin_ps, t0)
+    assert np.array_equal(h.astype(np.uint64), ref) and d == rd

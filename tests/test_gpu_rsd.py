@@ -1,13 +1,14 @@
 """GPU parity of nlos_rsd against the FP64 radial-RSD oracle (relative L2 <= 1e-4)."""
 import numpy as np
 import pytest
+import torch
 
 import scenes
 from oracle import rsd as orsd
 from oracle.metrics import argmax_index, rel_l2
-from paper_2608_28183_amd import runtime
+from paper_2608_28183_amd import nlos, runtime
 
-from gpu_util import run_rsd, say
+from gpu_util import run_rsd, say, to_dev
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -68,3 +69,26 @@ def test_rsd_fp16_kernel_storage(ctx):
     e = rel_l2(vol, rv)
     say("rsd c1 K_r fp16 rel_l2", e)
     assert e < 2e-3 and argmax_index(vol) == argmax_index(rv)
+
+
+def test_rsd_depth_major_layout_and_plan_workspace(ctx):
+    """vol_depth_major writes the same magnitudes as a stack of depth planes, bit for bit,
+    and the plan's workspace query equals the descriptor's."""
+    cfg = scenes.CONFIGS["c1"]
+    tau = to_dev(scenes.config_transient("c1"))
+    p = scenes.rsd_params(cfg)
+    args = (ctx, cfg.ny, cfg.nx, cfg.nt, cfg.dx, cfg.dy, cfg.bin_ps, 2, p.freq_bins, p.weights, p.n_depth,
+            p.depth0, p.depth_step)
+    a = runtime.RsdPlan(*args)
+    b = runtime.RsdPlan(*args, vol_depth_major=True)
+    assert a.ws_bytes == b.ws_bytes == nlos.nlos_rsd_desc_workspace_bytes(a.desc)
+    va = torch.empty((cfg.ny, cfg.nx, p.n_depth), device="cuda")
+    vb = torch.full((p.n_depth, cfg.ny, cfg.nx), -1.0, device="cuda")
+    ia = torch.empty((cfg.ny, cfg.nx), device="cuda")
+    ib = torch.empty((cfg.ny, cfg.nx), device="cuda")
+    a(tau, va, ia, a.workspace())
+    b(tau, vb, ib, b.workspace())
+    torch.cuda.synchronize()
+    assert torch.equal(vb, va.permute(2, 0, 1)) and torch.equal(ia, ib)
+    f = runtime.FkPlan(ctx, cfg.ny, cfg.nx, cfg.nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, 2)
+    assert f.ws_bytes == nlos.nlos_fk_desc_workspace_bytes(f.desc)
