@@ -250,7 +250,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fk_c4",
                     choices=["fk_c4", "fk_c3", "fk_c1", "fk_office", "rsd_c3", "rsd_c2", "rsd_office", "bin_c2", "phasor_c2", "moe_c4",
-                             "moe_c3", "merge_c4", "copy_1GiB"],
+                             "moe_c3", "merge_c4", "dda_c3", "copy_1GiB"],
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -377,6 +377,38 @@ def main():
         units_per_step = 1
         workload = {"workload": f"complex f-k field {ny}x{nx}x{nt} padded x{cfg.pad} + coherence merging "
                                 f"over {window} frames", "shape": [ny, nx, nt], "window": window}
+    elif kind == "dda":
+        # one frame = a radial RSD volume, then the depth-dependent average over the last 3
+        # volumes with the default table; the input alternates between two noise draws
+        taus = [torch.from_numpy(scenes.config_transient(cname)).to(dev),
+                torch.from_numpy(scenes.transient(cfg, seed=cfg.seed + 1)).to(dev)]
+        p = scenes.rsd_params(cfg)
+        plan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
+                               p.weights, p.n_depth, p.depth0, p.depth_step)
+        ws = plan.workspace()
+        vol = torch.empty((ny, nx, p.n_depth), device=dev)
+        avg = torch.empty((ny, nx, p.n_depth), device=dev)
+        img = torch.empty((ny, nx), device=dev)
+        window = 3
+        table = nlos.nlos_dda_default_weights(p.n_depth, window)
+        dstate = nlos.nlos_dda_create(ctx.handle, ny * nx, p.n_depth, window, table)
+        counter = [0]
+
+        def step():
+            plan(taus[counter[0] & 1], vol, None, ws)
+            nlos.nlos_dda_push(ctx.handle, dstate, vol, avg, img)
+            counter[0] += 1
+        g = nlos.nlos_rsd_geometry_get(plan.desc)
+        pass_bytes = rsd_pass_bytes(ny, nx, nt, cfg.pad, len(p.freq_bins), p.n_depth, g["n_rho"])
+        # new volume read, ring slot and average written, the older frames of non-zero weight
+        # read, the image written
+        older = sum(sum(1 for w in row[1:] if w != 0.0) for row in table)
+        pass_bytes["dda"] = 4 * ny * nx * (3 * p.n_depth + older + 1)
+        metric, unit = "dda_rsd_volumes_per_s", "volumes/s"
+        units_per_step = 1
+        workload = {"workload": f"radial RSD {ny}x{nx}x{nt} padded x{cfg.pad}, {p.n_depth} depths, then the "
+                                f"depth-dependent average over {window} volumes",
+                    "shape": [ny, nx, nt], "n_depth": p.n_depth, "window": window}
     elif kind == "phasor":
         ev = scenes.config_events(cname, "shuffled")
         d_ev = torch.from_numpy(np.frombuffer(ev.tobytes(), dtype=np.uint8).copy()).to(dev)

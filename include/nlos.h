@@ -53,6 +53,7 @@ typedef struct nlos_rsd_plan nlos_rsd_plan;
 typedef struct nlos_moe_plan nlos_moe_plan;
 typedef struct nlos_phasor_plan nlos_phasor_plan;
 typedef struct nlos_merge nlos_merge;
+typedef struct nlos_dda nlos_dda;
 typedef struct nlos_graph nlos_graph;
 
 /* ------------------------------------------------------------------------ */
@@ -98,7 +99,8 @@ typedef enum {
   NLOS_PASS_MOE_MIX = 16,      /* mixture of experts: Eq. 10 on the branch images */
   NLOS_PASS_PHASOR_BIN = 17,   /* phasors straight from photon records */
   NLOS_PASS_MERGE = 18,        /* coherence-weighted temporal merging */
-  NLOS_PASS_COUNT = 19
+  NLOS_PASS_DDA = 19,          /* depth-dependent temporal average */
+  NLOS_PASS_COUNT = 20
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
@@ -370,6 +372,36 @@ nlos_status nlos_merge_reset(nlos_merge *merge);
  * a state must not be pushed from two streams at once. */
 nlos_status nlos_merge_push(nlos_ctx *ctx, nlos_merge *merge, const float *d_frame, float *d_merged,
                             float *d_coherence);
+
+/* ------------------------------------------------------------------------ */
+/* Depth-dependent average of the last N_w volumes (Section 4.4, DDA)        */
+/* ------------------------------------------------------------------------ */
+
+/* The library's default weight table (host only; the paper leaves the weights open):
+ * weights[d * window + a] = 1 for a < n_d and 0 otherwise, a counting frames back from the
+ * newest, with n_d = 1 + floor((window - 1) d / (n_depth - 1) + 1/2) at depth index d
+ * (n_d = window when n_depth = 1): the nearest plane keeps only the newest frame, the
+ * farthest averages all window frames, since farther planes return less light.
+ * n_depth >= 1, 1 <= window <= 64, weights holds n_depth * window floats. */
+nlos_status nlos_dda_default_weights(int n_depth, int window, float *weights);
+/* DDA state over volumes of n_vox voxels x n_depth depths, depth fastest ([n_vox][n_depth]:
+ * the default layout of nlos_fk, whose depth axis is nt, and of nlos_rsd): a device ring of
+ * `window` (1..64) volumes, window * n_vox * n_depth * 4 bytes owned by the state, and a
+ * device copy of the host table weights[n_depth][window] (read at creation; entries finite
+ * and >= 0, weights[d * window] > 0 for every d, else NLOS_ERR_INVALID_ARG). */
+nlos_status nlos_dda_create(nlos_ctx *ctx, uint64_t n_vox, int n_depth, int window, const float *weights,
+                            nlos_dda **out);
+nlos_status nlos_dda_destroy(nlos_dda *dda);
+/* Forgets the frames pushed so far (host only). */
+nlos_status nlos_dda_reset(nlos_dda *dda);
+/* Adds frame i, d_vol[n_vox][n_depth] (read only), and over the m = min(i + 1, window)
+ * newest frames v_{i-a}, a < m, writes
+ *   d_avg[v][d] = sum_a W[d][a] v_{i-a}[v][d] / sum_a W[d][a]   (nullable),
+ *   d_img[v]    = max over d of d_avg[v][d]                      (nullable; not both NULL).
+ * All pointers 4-byte aligned device memory; d_vol must not overlap the outputs.  Calls on
+ * one state are ordered by the context's stream; a state must not be pushed from two
+ * streams at once. */
+nlos_status nlos_dda_push(nlos_ctx *ctx, nlos_dda *dda, const float *d_vol, float *d_avg, float *d_img);
 
 /* Graph replay (the paper records each frame's launch sequence into a graph and replays
  * it, Section 2.2, and measures the gain in its ablations, Section 5.2): captures one

@@ -265,7 +265,7 @@ static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
     "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale",
-    "moe_phasor", "moe_mix", "phasor_bin", "merge"};
+    "moe_phasor", "moe_mix", "phasor_bin", "merge", "dda"};
 
 extern "C" {
 
@@ -1388,6 +1388,116 @@ nlos_status nlos_merge_push(nlos_ctx* ctx, nlos_merge* m, const float* d_frame, 
   HIP_TRY(ctx, timed(ctx, NLOS_PASS_MERGE, [&] {
     return nlos::launch_merge(reinterpret_cast<const float2*>(d_frame), m->ring, m->n, m->window, slot, first, count,
                               m->eps, d_merged, d_coherence, ctx->stream);
+  }));
+  ++m->pushed;
+  return NLOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// depth-dependent average (Section 4.4, DDA)
+// ---------------------------------------------------------------------------
+
+struct nlos_dda {
+  int device = 0;
+  long long nvox = 0;
+  int nd = 0;
+  int window = 0;
+  long long pushed = 0;    // frames since the last reset
+  float* ring = nullptr;   // [window][nvox][nd]
+  float* w = nullptr;      // [nd][window]
+};
+
+nlos_status nlos_dda_default_weights(int n_depth, int window, float* weights) {
+  if (n_depth < 1 || window < 1 || window > 64 || !weights)
+    return fail(nullptr, NLOS_ERR_INVALID_ARG, "dda_default_weights: need n_depth >= 1, window in [1, 64]");
+  for (int d = 0; d < n_depth; ++d) {
+    // n_d = 1 + floor((window - 1) d / (n_depth - 1) + 1/2), in integers
+    const long long nd = n_depth == 1 ? window
+                                      : 1 + (2LL * (window - 1) * d + (n_depth - 1)) / (2LL * (n_depth - 1));
+    for (int a = 0; a < window; ++a) weights[(size_t)d * window + a] = a < nd ? 1.f : 0.f;
+  }
+  return NLOS_OK;
+}
+
+nlos_status nlos_dda_create(nlos_ctx* ctx, uint64_t n_vox, int n_depth, int window, const float* weights,
+                            nlos_dda** out) {
+  try {
+    if (!ctx || !out || !weights) return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_create: NULL argument");
+    if (n_vox == 0 || n_depth < 1 || window < 1 || window > 64)
+      return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_create: need n_vox >= 1, n_depth >= 1, window in [1, 64]");
+    if (n_vox > (1ull << 40) / (uint64_t)n_depth)
+      return fail(ctx, NLOS_ERR_UNSUPPORTED, "dda_create: volume too large");
+    for (int d = 0; d < n_depth; ++d)
+      for (int a = 0; a < window; ++a) {
+        const float v = weights[(size_t)d * window + a];
+        if (!std::isfinite(v) || v < 0.f || (a == 0 && !(v > 0.f)))
+          return fail(ctx, NLOS_ERR_INVALID_ARG,
+                      "dda_create: weights must be finite and >= 0, with weights[d][0] > 0 (d %d, a %d: %g)", d, a,
+                      (double)v);
+      }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    nlos::host_alloc_point();
+    nlos_dda* m = new (std::nothrow) nlos_dda();
+    if (!m) return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "dda_create: host allocation");
+    m->device = ctx->device;
+    m->nvox = (long long)n_vox;
+    m->nd = n_depth;
+    m->window = window;
+    const size_t wbytes = (size_t)n_depth * window * sizeof(float);
+    hipError_t e = nlos::dev_alloc((void**)&m->ring, (size_t)window * n_vox * n_depth * sizeof(float));
+    if (e == hipSuccess) e = nlos::dev_alloc((void**)&m->w, wbytes);
+    if (e == hipSuccess) e = hipMemcpy(m->w, weights, wbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      nlos_dda_destroy(m);
+      return fail(ctx, e == hipErrorOutOfMemory ? NLOS_ERR_OUT_OF_MEMORY : NLOS_ERR_DEVICE, "dda_create: %s",
+                  hipGetErrorString(e));
+    }
+    *out = m;
+    return NLOS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, NLOS_ERR_OUT_OF_MEMORY, "nlos_dda_create: host allocation failed");
+  }
+}
+
+nlos_status nlos_dda_destroy(nlos_dda* m) {
+  if (!m) return NLOS_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  if (m->ring) (void)hipFree(m->ring);
+  if (m->w) (void)hipFree(m->w);
+  delete m;
+  return NLOS_OK;
+}
+
+nlos_status nlos_dda_reset(nlos_dda* m) {
+  if (!m) return fail(nullptr, NLOS_ERR_INVALID_ARG, "dda_reset: NULL");
+  m->pushed = 0;
+  return NLOS_OK;
+}
+
+nlos_status nlos_dda_push(nlos_ctx* ctx, nlos_dda* m, const float* d_vol, float* d_avg, float* d_img) {
+  if (!ctx || !m) return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: ctx or state is NULL");
+  if (!d_vol) return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: d_vol is NULL");
+  if (!d_avg && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: d_avg and d_img are both NULL");
+  if (reinterpret_cast<uintptr_t>(d_vol) % 4 != 0 || reinterpret_cast<uintptr_t>(d_avg) % 4 != 0 ||
+      reinterpret_cast<uintptr_t>(d_img) % 4 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: buffers must be 4-byte aligned");
+  if (m->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: state of another device");
+  const size_t nv = (size_t)m->nvox * m->nd;
+  const char* vb = reinterpret_cast<const char*>(d_vol);
+  const char* ve = vb + nv * sizeof(float);
+  auto overlaps = [&](const void* p, size_t n) {
+    const char* b = static_cast<const char*>(p);
+    return p != nullptr && b < ve && vb < b + n * sizeof(float);
+  };
+  if (overlaps(d_avg, nv) || overlaps(d_img, (size_t)m->nvox))
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "dda_push: d_vol overlaps an output");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int slot = (int)(m->pushed % m->window);
+  const int count = (int)std::min<long long>(m->pushed + 1, m->window);
+  HIP_TRY(ctx, timed(ctx, NLOS_PASS_DDA, [&] {
+    return nlos::launch_dda(d_vol, m->ring, m->w, m->nvox, m->nd, m->window, slot, count, d_avg, d_img,
+                            ctx->stream);
   }));
   ++m->pushed;
   return NLOS_OK;

@@ -140,6 +140,10 @@ hipError_t launch_moe_phasor_pair(const MoePhasorArgs& a, const float2* tw, hipS
 // slots first, first + 1, ... mod window, oldest first)
 hipError_t launch_merge(const float2* frame, float2* ring, long long n, int window, int slot, int first,
                         int count, float eps, float* merged, float* coherence, hipStream_t s);
+// Depth-dependent average: stores vol (nvox x nd, depth fastest) into ring slot `slot` and
+// averages the `count` newest frames with weights w[nd][window] (avg, img nullable).
+hipError_t launch_dda(const float* vol, float* ring, const float* w, long long nvox, int nd, int window, int slot,
+                      int count, float* avg, float* img, hipStream_t s);
 // img = max-normalised fk_img * (max-normalised rsd_img + eps)^beta, max-normalised
 // (images of n pixels; mx: 3 words of device scratch)
 hipError_t launch_moe_mix(const float* fk_img, const float* rsd_img, float* img, int n, float beta,

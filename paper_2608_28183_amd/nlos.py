@@ -113,6 +113,12 @@ _SIGNATURES = {
     "nlos_merge_destroy": (_ST, [_VP]),
     "nlos_merge_reset": (_ST, [_VP]),
     "nlos_merge_push": (_ST, [_VP, _VP, _VP, _VP, _VP]),
+    "nlos_dda_default_weights": (_ST, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
+    "nlos_dda_create": (_ST, [_VP, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(_VP)]),
+    "nlos_dda_destroy": (_ST, [_VP]),
+    "nlos_dda_reset": (_ST, [_VP]),
+    "nlos_dda_push": (_ST, [_VP, _VP, _VP, _VP, _VP]),
     "nlos_moe_check": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc), ctypes.c_double,
                              ctypes.c_double]),
     "nlos_moe_workspace_bytes": (_ST, [ctypes.POINTER(nlos_fk_desc), ctypes.POINTER(nlos_rsd_desc),
@@ -204,7 +210,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 19
+NLOS_PASS_COUNT = 20
 
 
 def nlos_pass_name(p: int) -> str:
@@ -479,3 +485,33 @@ def nlos_merge_reset(merge: int) -> None:
 
 def nlos_merge_push(ctx: int, merge: int, frame, merged, coherence=None) -> None:
     _check(lib().nlos_merge_push(ctx, merge, _ptr(frame), _ptr(merged), _ptr(coherence)), "nlos_merge_push", ctx)
+
+
+def nlos_dda_default_weights(n_depth: int, window: int):
+    """The library's default table as a list of n_depth rows of `window` floats."""
+    buf = (ctypes.c_float * (n_depth * window))()
+    _check(lib().nlos_dda_default_weights(n_depth, window, buf), "nlos_dda_default_weights")
+    return [list(buf[d * window:(d + 1) * window]) for d in range(n_depth)]
+
+
+def nlos_dda_create(ctx: int, n_vox: int, n_depth: int, window: int, weights) -> int:
+    """weights: n_depth rows of `window` values (any nested sequence or array)."""
+    flat = [float(v) for row in weights for v in row]
+    if len(flat) != n_depth * window:
+        raise ValueError("weights must hold n_depth x window values")
+    buf = (ctypes.c_float * len(flat))(*flat)
+    out = ctypes.c_void_p()
+    _check(lib().nlos_dda_create(ctx, n_vox, n_depth, window, buf, ctypes.byref(out)), "nlos_dda_create", ctx)
+    return out.value
+
+
+def nlos_dda_destroy(dda: int) -> None:
+    _check(lib().nlos_dda_destroy(dda), "nlos_dda_destroy")
+
+
+def nlos_dda_reset(dda: int) -> None:
+    _check(lib().nlos_dda_reset(dda), "nlos_dda_reset")
+
+
+def nlos_dda_push(ctx: int, dda: int, vol, avg=None, img=None) -> None:
+    _check(lib().nlos_dda_push(ctx, dda, _ptr(vol), _ptr(avg), _ptr(img)), "nlos_dda_push", ctx)

@@ -1,4 +1,5 @@
 """The C-ABI library: exports, host-side validation and plan-time math (no GPU)."""
+import ctypes
 import json
 import math
 import os
@@ -300,3 +301,17 @@ def test_injected_host_allocation_failure_leaves_the_library_usable():
         nlos.nlos_debug_fail_allocations(0)
     again = nlos.nlos_rsd_kernel_host(d)
     assert np.array_equal(again, ref)
+
+
+@pytest.mark.parametrize("n_depth,window", [(64, 3), (9, 5), (2, 4), (1, 6), (100, 1), (512, 64), (7, 64)])
+def test_dda_default_weights_match_the_oracle_table(n_depth, window):
+    from oracle import dda as odda
+    got = np.array(nlos.nlos_dda_default_weights(n_depth, window), dtype=np.float64)
+    np.testing.assert_array_equal(got, odda.default_weights(n_depth, window))
+
+
+def test_dda_default_weights_validation():
+    buf = (ctypes.c_float * 4)()
+    for nd, w in [(0, 2), (2, 0), (2, 65)]:
+        assert nlos.lib().nlos_dda_default_weights(nd, w, buf) == nlos.NLOS_ERR_INVALID_ARG
+    assert nlos.lib().nlos_dda_default_weights(2, 2, None) == nlos.NLOS_ERR_INVALID_ARG
