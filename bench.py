@@ -24,6 +24,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 F32_VALU_PEAK_TFLOPS = 157.3
+MFMA_F16_PEAK_TFLOPS = 2500.0  # dense FP16 / BF16 matrix cores
 
 
 def fk_pass_bytes(ny, nx, nt, pad, c=8, xfirst=True):
@@ -61,7 +62,7 @@ def fk_full_schedule_bytes(ny, nx, nt, pad):
         (c * ny * Mx * nt + 4 * ny * nx * nt)
 
 
-def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
+def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0, kernel_bytes=8):
     """Algorithmic bytes of each RSD pass (frequency / depth contiguous layout)."""
     Mx, My = pad * nx, pad * ny
     c = 8
@@ -70,7 +71,8 @@ def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0):
         "rsd_x": c * ny * nx * nf + c * ny * Mx * nf,
         "rsd_y": c * ny * Mx * nf + c * My * Mx * nf,
         # spectra, kernel rows (read at least once), pixel chunks and the propagated planes
-        "rsd_propagate": c * My * Mx * nf + c * nrho * nf * nd + (4 + 12 * 64) * nchunks + c * My * Mx * nd,
+        "rsd_propagate": c * My * Mx * nf + kernel_bytes * nrho * nf * nd + (4 + 12 * 64) * nchunks
+        + c * My * Mx * nd,
         "rsd_yi": c * My * Mx * nd + c * ny * Mx * nd,
         "rsd_xi": c * ny * Mx * nd + 4 * ny * nx * nd + 4 * ny * nx,
         "fill": 4 * ny * nx,
@@ -254,7 +256,8 @@ def main():
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
-                    help="f-k storage precision of the complex intermediates")
+                    help="f-k: storage precision of the complex intermediates; RSD: storage of the "
+                         "radial kernel (FP16 / BF16 propagate on the matrix cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
@@ -306,13 +309,17 @@ def main():
                                else scenes.transient(cfg)).to(dev)
         p = scenes.rsd_params(cfg)
         plan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
-                               p.weights, p.n_depth, p.depth0, p.depth_step)
+                               p.weights, p.n_depth, p.depth0, p.depth_step, kernel_prec=args.prec)
         ws = plan.workspace()
         vol = torch.empty((ny, nx, p.n_depth), device=dev)
         img = torch.empty((ny, nx), device=dev)
         step = lambda: plan(tau, vol, img, ws)  # noqa: E731
         g = nlos.nlos_rsd_geometry_get(plan.desc)
-        pass_bytes = rsd_pass_bytes(ny, nx, nt, cfg.pad, len(p.freq_bins), p.n_depth, g["n_rho"])
+        pass_bytes = rsd_pass_bytes(ny, nx, nt, cfg.pad, len(p.freq_bins), p.n_depth, g["n_rho"],
+                                    kernel_bytes=8 if args.prec == "fp32" else 4)
+        # the propagation's arithmetic: per padded pixel, frequency, depth and radial tap one
+        # complex multiply-add (8 flops)
+        prop_flops = 16 * (cfg.pad * ny) * (cfg.pad * nx) * len(p.freq_bins) * p.n_depth
         metric, unit = "rsd_volumes_per_s", "volumes/s"
         units_per_step = 1
         workload = {"workload": f"radial RSD {ny}x{nx}x{nt} padded x{cfg.pad}, "
@@ -492,6 +499,16 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": pass_bytes[dom], "avg_ms": round(avg_ms[dom], 4)}
+    if kind == "rsd" and dom == "rsd_propagate":
+        # the propagation is a contraction: priced against the arithmetic peak it runs on
+        # (matrix cores for FP16 / BF16 kernels, FP32 FMAs otherwise), bytes kept beside
+        tflops = prop_flops / (avg_ms[dom] * 1e-3) / 1e12
+        peak = MFMA_F16_PEAK_TFLOPS if args.prec != "fp32" else F32_VALU_PEAK_TFLOPS
+        roofline = {"bound": "mfma" if args.prec != "fp32" else "alu", "kernel": dom,
+                    "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tflops / peak, 4), "traffic": traffic, "algorithmic_flops": prop_flops,
+                    "avg_ms": round(avg_ms[dom], 4), "hbm_GBps": round(achieved, 1),
+                    "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": pass_bytes[dom]}
     total_alg = sum(v for k, v in pass_bytes.items())
     print(f"[bench] {args.steps} steps: {sec*1e3:.3f} ms/step; passes (avg ms): "
           + ", ".join(f"{k} {v:.3f}" for k, v in avg_ms.items()), file=sys.stderr, flush=True)

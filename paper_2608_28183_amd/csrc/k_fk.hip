@@ -407,8 +407,8 @@ __global__ __launch_bounds__(256) void fk_l1_partial(const float2* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void fk_scale_exponents(const float* __restrict__ partials, int np,
-                                                          int* __restrict__ exps, int l_norm, int l_my,
-                                                          int l_mx) {
+                                                          int* __restrict__ exps, int l_norm, int l_first_inv,
+                                                          int l_second_inv) {
   __shared__ float red[4];
   float acc = 0.f;
   for (int j = threadIdx.x; j < np; j += 256) acc += partials[j];
@@ -417,15 +417,16 @@ __global__ __launch_bounds__(256) void fk_scale_exponents(const float* __restric
     int k = 0;
     if (B > 0.f && B <= 3.0e38f) frexpf(B, &k);
     const int ef = (B > 0.f && B <= 3.0e38f) ? 14 - k : 0;
-    exps[0] = ef;                    // W1, W2: bound B
-    exps[1] = ef + l_norm;           // W3: bound B / (Mx My Mt)
-    exps[2] = exps[1] - l_my;        // W4: bound My B / (Mx My Mt)
-    exps[3] = exps[2] - l_mx;        // W5: bound Mx My B / (Mx My Mt)
+    // the inverse passes run x first (length Mx), then y (length My)
+    exps[0] = ef;                        // W1, W2: bound B
+    exps[1] = ef + l_norm;               // W3: bound B / (Mx My Mt)
+    exps[2] = exps[1] - l_first_inv;     // W4 (after the x-IFFT): bound Mx B / (Mx My Mt)
+    exps[3] = exps[2] - l_second_inv;    // W5 (after the y-IFFT): bound Mx My B / (Mx My Mt)
   }
 }
 
 hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
-                            int l_norm, int l_my, int l_mx, hipStream_t s) {
+                            int l_norm, int l_first_inv, int l_second_inv, hipStream_t s) {
   if (n % 2 != 0 || (nt & (nt - 1)) != 0 || nt < 2) return hipErrorInvalidValue;
   const float tscale = (float)(1.0 / (double)(nt - 1));
   hipLaunchKernelGGL(fk_l1_partial, dim3(kScaleBlocks), dim3(256), 0, s,
@@ -433,7 +434,7 @@ hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partia
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fk_scale_exponents, dim3(1), dim3(256), 0, s, partials, kScaleBlocks, exps, l_norm,
-                     l_my, l_mx);
+                     l_first_inv, l_second_inv);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 // element is produced by one lane in a fixed frequency order.
 #include <hip/hip_fp16.h>
 
+#include "mfma_fft.hpp"
 #include "nlos_internal.hpp"
 
 namespace nlos {
@@ -21,13 +22,12 @@ constexpr int kGroupPix = 64;   // pixels per chunk (one per lane; matches the p
 constexpr int kDepths = 8;      // depths per wave
 constexpr int kWavesPerBlock = 4;
 
-template <bool FP16>
+template <int SP>
 __device__ __forceinline__ float2 load_kr(const void* __restrict__ kr, long long i) {
-  if constexpr (FP16) {
-    const __half2 h = static_cast<const __half2*>(kr)[i];
-    return __half22float2(h);
-  } else {
+  if constexpr (SP == SP_F32) {
     return static_cast<const float2*>(kr)[i];
+  } else {
+    return Mfma<SP>::unpack(static_cast<const unsigned int*>(kr)[i]);
   }
 }
 
@@ -39,17 +39,17 @@ __device__ __forceinline__ void cmac2(float2& acc, float2 pa, float2 k0, float2 
 
 // One frequency f of the lane's pixel: tap-weighted phasors, then the ND depths of the
 // wave's slice (kernel rows o0, o1 are wave-uniform).
-template <bool FP16, int ND>
+template <int SP, int ND>
 __device__ __forceinline__ void rsd_freq(float2* acc, float2 p, float2 wf, float wa, float wb, const void* kr,
                                          long long o0, long long o1) {
   const float2 pw = make_float2(p.x * wf.x - p.y * wf.y, p.x * wf.y + p.y * wf.x);
   const float2 pa = make_float2(pw.x * wa, pw.y * wa);
   const float2 pb = make_float2(pw.x * wb, pw.y * wb);
 #pragma unroll
-  for (int j = 0; j < ND; ++j) cmac2(acc[j], pa, load_kr<FP16>(kr, o0 + j), pb, load_kr<FP16>(kr, o1 + j));
+  for (int j = 0; j < ND; ++j) cmac2(acc[j], pa, load_kr<SP>(kr, o0 + j), pb, load_kr<SP>(kr, o1 + j));
 }
 
-template <bool FP16>
+template <int SP>
 __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
   const int lane = threadIdx.x & 63;
   // wave-uniform work index: chunk g, depth slice starting at d0
@@ -82,13 +82,13 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
         for (int u = 0; u < 8; ++u) p[u] = ph[f + u];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          rsd_freq<FP16, kDepths>(acc, p[u], a.w[f + u], wa, wb, a.Kr, o0, o1);
+          rsd_freq<SP, kDepths>(acc, p[u], a.w[f + u], wa, wb, a.Kr, o0, o1);
           o0 += Nd;
           o1 += Nd;
         }
       }
       for (; f < Nf; ++f) {
-        rsd_freq<FP16, kDepths>(acc, ph[f], a.w[f], wa, wb, a.Kr, o0, o1);
+        rsd_freq<SP, kDepths>(acc, ph[f], a.w[f], wa, wb, a.Kr, o0, o1);
         o0 += Nd;
         o1 += Nd;
       }
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
         const float2 pb = make_float2(pw.x * wb, pw.y * wb);
 #pragma unroll
         for (int j = 0; j < kDepths; ++j)
-          if (j < nd) cmac2(acc[j], pa, load_kr<FP16>(a.Kr, o0 + j), pb, load_kr<FP16>(a.Kr, o1 + j));
+          if (j < nd) cmac2(acc[j], pa, load_kr<SP>(a.Kr, o0 + j), pb, load_kr<SP>(a.Kr, o1 + j));
         o0 += Nd;
         o1 += Nd;
       }
@@ -115,16 +115,203 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
     if (d0 + j < Nd) out[j] = acc[j];
 }
 
+// ---------------------------------------------------------------------------
+// matrix-core propagation (FP16 / BF16 radial kernel)
+// ---------------------------------------------------------------------------
+//
+// For one chunk the sum is a complex matrix product: rows = the chunk's 64 pixels, the
+// contraction runs over (frequency, tap) with the tap-weighted phasors A[p][f, tap] =
+// w_f P^[p][f] (wa | wb)[p] on one side and the kernel rows K_r[i0 | i1][f][d] on the
+// other, columns = depths.  As a real product on (re, im) pairs it maps onto
+// v_mfma_f32_32x32x16 (FP32 accumulate): one 16-wide K step covers 4 frequencies x 2
+// taps x (re, im), lane l holding frequencies 4s + 2(l/32) + {0, 1}.  B comes straight
+// from the stored kernel pairs: (re, -im) for the real part of the output, (im, re) for
+// the imaginary part.  A is rounded to the kernel's format after scaling by a power of two
+// 2^e chosen per chunk from the largest |w_f P^| (wa | wb) of its pixels (a first pass
+// over their rows), so that every component stays below 2^14; the FP32 result is
+// multiplied by 2^-e.  A wave takes one chunk and DT 32-depth tiles.
+
+template <int SP, int DT>
+__global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
+  using M = Mfma<SP>;
+  const int lane = threadIdx.x & 63;
+  const int hl = lane >> 5, c32 = lane & 31;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nds = (a.Nd + 32 * DT - 1) / (32 * DT);
+  const long long w = (long long)blockIdx.x * kWavesPerBlock + wib;
+  if (w >= a.nchunks * nds) return;
+  const long long g = w / nds;
+  const int d0 = (int)(w % nds) * 32 * DT;
+  const int Nf = a.Nf, Nd = a.Nd;
+  const int i0 = a.chunk_i0[g];
+  // the lane's own pixel (first pass, stores) and the two rows it feeds into A
+  const int pix = a.chunk_pix[g * kGroupPix + lane];
+  const int pr0 = a.chunk_pix[g * kGroupPix + c32], pr1 = a.chunk_pix[g * kGroupPix + 32 + c32];
+  mf_acc acc[2][DT][2];  // [row tile][depth tile][re | im]
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < DT; ++q)
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[r][q][o][v] = 0.f;
+  float inv_scale = 1.f;
+  if (i0 >= 0) {
+    const int i1 = i0 + 1 < a.cut_idx ? i0 + 1 : a.cut_idx;
+    // pass 1: the largest component of w_f P^ times the larger tap weight
+    float m = 0.f;
+    {
+      const float tw = fmaxf(a.chunk_wa[g * kGroupPix + lane], a.chunk_wb[g * kGroupPix + lane]);
+      const float2* ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
+      constexpr int U = 16;  // loads in flight per lane (unconditional, clamped indices:
+                             // a repeated last frequency does not change the maximum)
+      for (int f0 = 0; f0 < Nf; f0 += U) {
+        float2 p[U], wf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int f = min(f0 + u, Nf - 1);
+          p[u] = ph[f];
+          wf[u] = a.w[f];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float re = p[u].x * wf[u].x - p[u].y * wf[u].y, im = p[u].x * wf[u].y + p[u].y * wf[u].x;
+          m = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+      m *= tw;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    }
+    int ex = 0;
+    if (m > 0.f) (void)frexpf(m, &ex);  // m < 2^ex
+    // clamped so that the scaled tap weights (<= 1) and 2^-e stay finite normal floats
+    const int e = min(max(14 - ex, -100), 100);
+    inv_scale = ldexpf(1.f, -e);
+    const float wa0 = ldexpf(a.chunk_wa[g * kGroupPix + c32], e), wb0 = ldexpf(a.chunk_wb[g * kGroupPix + c32], e);
+    const float wa1 = ldexpf(a.chunk_wa[g * kGroupPix + 32 + c32], e);
+    const float wb1 = ldexpf(a.chunk_wb[g * kGroupPix + 32 + c32], e);
+    const float2* ph0 = a.Ph + (long long)(pr0 >= 0 ? pr0 : 0) * a.ph_stride;
+    const float2* ph1 = a.Ph + (long long)(pr1 >= 0 ? pr1 : 0) * a.ph_stride;
+    const unsigned int* kr = static_cast<const unsigned int*>(a.Kr);
+    const long long k0 = (long long)i0 * Nf * Nd, k1 = (long long)i1 * Nf * Nd;
+    // one K step: this lane's frequencies fa = f0, fb = f0 + 1.  Every load is
+    // unconditional, from clamped (valid) indices, so that the loads of several steps stay
+    // in flight: a frequency beyond Nf is zeroed by its multiplier ma / mb on w_f P^ (its
+    // A entries are then 0, whatever kernel value it meets), and a depth beyond Nd only
+    // feeds output columns that are never stored.
+    struct Step {
+      float2 wfa, wfb, pa0, pb0, pa1, pb1;
+      float ma, mb;
+      unsigned int kv[DT][4];  // [depth tile][K0a, K1a, K0b, K1b]
+    };
+    auto load = [&](int f0) {
+      Step t;
+      const int fa = min(f0, Nf - 1), fb = min(f0 + 1, Nf - 1);
+      t.ma = f0 < Nf ? 1.f : 0.f;
+      t.mb = f0 + 1 < Nf ? 1.f : 0.f;
+      t.wfa = a.w[fa];
+      t.wfb = a.w[fb];
+      t.pa0 = ph0[fa];
+      t.pb0 = ph0[fb];
+      t.pa1 = ph1[fa];
+      t.pb1 = ph1[fb];
+#pragma unroll
+      for (int q = 0; q < DT; ++q) {
+        const int d = min(d0 + 32 * q + c32, Nd - 1);
+        t.kv[q][0] = kr[k0 + (long long)fa * Nd + d];
+        t.kv[q][1] = kr[k1 + (long long)fa * Nd + d];
+        t.kv[q][2] = kr[k0 + (long long)fb * Nd + d];
+        t.kv[q][3] = kr[k1 + (long long)fb * Nd + d];
+      }
+      return t;
+    };
+    auto cm = [](float2 p, float2 wf) { return make_float2(p.x * wf.x - p.y * wf.y, p.x * wf.y + p.y * wf.x); };
+    auto step = [&](const Step& t) {
+      const float2 wa_ = make_float2(t.wfa.x * t.ma, t.wfa.y * t.ma), wb_ = make_float2(t.wfb.x * t.mb, t.wfb.y * t.mb);
+      const float2 za0 = cm(t.pa0, wa_), zb0 = cm(t.pb0, wb_), za1 = cm(t.pa1, wa_), zb1 = cm(t.pb1, wb_);
+      mf_u4 A[2];
+      A[0] = mf_u4{M::pack(za0.x * wa0, za0.y * wa0), M::pack(za0.x * wb0, za0.y * wb0),
+                   M::pack(zb0.x * wa0, zb0.y * wa0), M::pack(zb0.x * wb0, zb0.y * wb0)};
+      A[1] = mf_u4{M::pack(za1.x * wa1, za1.y * wa1), M::pack(za1.x * wb1, za1.y * wb1),
+                   M::pack(zb1.x * wa1, zb1.y * wa1), M::pack(zb1.x * wb1, zb1.y * wb1)};
+#pragma unroll
+      for (int q = 0; q < DT; ++q) {
+        // (re, -im): flip the sign of the upper half; (im, re): swap the halves
+        const unsigned int* kq = t.kv[q];
+        const mf_u4 Bre = mf_u4{kq[0] ^ 0x80000000u, kq[1] ^ 0x80000000u, kq[2] ^ 0x80000000u, kq[3] ^ 0x80000000u};
+        const mf_u4 Bim = mf_u4{(kq[0] >> 16) | (kq[0] << 16), (kq[1] >> 16) | (kq[1] << 16),
+                                (kq[2] >> 16) | (kq[2] << 16), (kq[3] >> 16) | (kq[3] << 16)};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          acc[r][q][0] = M::mma(A[r], Bre, acc[r][q][0]);
+          acc[r][q][1] = M::mma(A[r], Bim, acc[r][q][1]);
+        }
+      }
+    };
+    // K steps s = 0 .. ns-1 (frequencies 4s + 2hl + {0, 1}); the loads of step s + 4 are
+    // issued right after step s is consumed, so four steps of loads are in flight
+    const int ns = (Nf + 3) / 4;
+    const int fl = 2 * hl;
+    Step b0 = load(fl), b1 = load(fl + 4), b2 = load(fl + 8), b3 = load(fl + 12);
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+      step(b0);
+      b0 = load(fl + 4 * (s0 + 4));
+      if (s0 + 1 < ns) step(b1);
+      b1 = load(fl + 4 * (s0 + 5));
+      if (s0 + 2 < ns) step(b2);
+      b2 = load(fl + 4 * (s0 + 6));
+      if (s0 + 3 < ns) step(b3);
+      b3 = load(fl + 4 * (s0 + 7));
+    }
+  }
+  // D lane layout: rows 8(v/4) + 4 hl + v%4 of the tile, column c32
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 32 * r + 8 * (v >> 2) + 4 * hl + (v & 3);
+      const int pp = __shfl(pix, row, 64);
+#pragma unroll
+      for (int q = 0; q < DT; ++q) {
+        const int d = d0 + 32 * q + c32;
+        if (pp >= 0 && d < Nd)
+          a.C[(long long)pp * a.c_stride + d] =
+              make_float2(acc[r][q][0][v] * inv_scale, acc[r][q][1][v] * inv_scale);
+      }
+    }
+}
+
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
+  if (a.mfma && (a.kernel_sp == SP_F16 || a.kernel_sp == SP_BF16)) {
+    // depth tiles per wave: two unless a.mfma asks for one or one covers every depth
+    const int dt = (a.mfma == 2 || a.Nd <= 32) ? 1 : 2;
+    const long long waves = a.nchunks * ((a.Nd + 32 * dt - 1) / (32 * dt));
+    const long long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (a.kernel_sp == SP_F16) {
+      if (dt == 1) hipLaunchKernelGGL((rsd_propagate_mfma<SP_F16, 1>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((rsd_propagate_mfma<SP_F16, 2>), grid, dim3(256), 0, s, a);
+    } else {
+      if (dt == 1) hipLaunchKernelGGL((rsd_propagate_mfma<SP_BF16, 1>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((rsd_propagate_mfma<SP_BF16, 2>), grid, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   const long long nds = (a.Nd + kDepths - 1) / kDepths;
   const long long waves = a.nchunks * nds;
   const long long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (a.kernel_fp16)
-    hipLaunchKernelGGL(rsd_propagate<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (a.kernel_sp == SP_F16)
+    hipLaunchKernelGGL(rsd_propagate<SP_F16>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else if (a.kernel_sp == SP_BF16)
+    hipLaunchKernelGGL(rsd_propagate<SP_BF16>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(rsd_propagate<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(rsd_propagate<SP_F32>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

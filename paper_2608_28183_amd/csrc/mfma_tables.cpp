@@ -11,8 +11,6 @@
 
 namespace nlos {
 
-namespace {
-
 uint16_t to_f16_bits(double v) {
   const _Float16 h = (_Float16)v;  // one rounding, to nearest even
   uint16_t u;
@@ -27,6 +25,8 @@ uint16_t to_bf16_bits(double v) {
   u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
   return (uint16_t)(u >> 16);
 }
+
+namespace {
 
 // Entry (c, k; n, cin) of the real form of F[k][n] = scale exp(-+2 pi i k n / R):
 // output part c (0 re, 1 im) of complex output k, input part cin of complex input n.

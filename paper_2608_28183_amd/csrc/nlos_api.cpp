@@ -173,6 +173,8 @@ struct nlos_ctx {
   void* d_mfma = nullptr;             // matrix-core DFT operands (FP64-built)
   nlos::MfmaTables mt{};
   bool mfma = true;                   // four-byte f-k passes on the matrix cores
+  int rsd_mfma = 1;                   // FP16 / BF16 radial kernels on the matrix cores (0 no; 2 one
+                                      // depth tile per wave)
 };
 
 struct nlos_fk_plan {
@@ -372,6 +374,8 @@ nlos_status nlos_create(int device, void* hip_stream, nlos_ctx** out) {
     }
     const char* mf = std::getenv("NLOS_FK_MFMA");
     c->mfma = !(mf && mf[0] == '0');
+    const char* rm = std::getenv("NLOS_RSD_MFMA");
+    c->rsd_mfma = (rm && (rm[0] == '0' || rm[0] == '2')) ? rm[0] - '0' : 1;
     *out = c;
     return NLOS_OK;
   } catch (const std::bad_alloc&) {
@@ -711,7 +715,8 @@ static nlos_status fk_run(nlos_ctx* ctx, const nlos_fk_plan* p, hipStream_t s, c
     // W4 follows the x-IFFT (its bound gains Mx), W5 the y-IFFT as well
     const int l_my = ilog2((int)My), l_mx = ilog2((int)Mx), l_norm = l_my + l_mx + ilog2(p->Mt);
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FK_SCALE, [&] {
-      return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, l_mx, l_my, s);
+      return nlos::launch_fk_scales(d_tau, ny * nx * nt, (int)nt, partials, ex, l_norm, /*first inverse*/ l_mx,
+                                    /*second inverse*/ l_my, s);
     }));
   }
   // pass 1: x-FFT of tau * t/(nt-1), zero padded to Mx, kx in [0, Mx/2]
@@ -918,8 +923,6 @@ nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
   for (int f = 0; f < 2 * d->n_freq; ++f)
     if (!std::isfinite(d->w[f])) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: w is not finite");
   if (d->data_prec != NLOS_FP32) return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: only FP32 data is built");
-  if (d->kernel_prec == NLOS_BF16)
-    return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: kernel storage is FP32 or FP16");
   return NLOS_OK;
 }
 
@@ -1019,12 +1022,14 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
                   hipGetErrorString(e));
     };
     hipError_t e;
-    if (d->kernel_prec == NLOS_FP16) {
-      // FP64 accumulation, a single rounding to binary16 on store
-      std::vector<_Float16> kh(2 * nk);
+    if (d->kernel_prec == NLOS_FP16 || d->kernel_prec == NLOS_BF16) {
+      // FP64 accumulation, a single rounding (to nearest even) to binary16 or bfloat16 on
+      // store; (re, im) pairs, re in the lower half
+      std::vector<uint16_t> kh(2 * nk);
+      const bool bf = d->kernel_prec == NLOS_BF16;
       for (size_t i = 0; i < nk; ++i) {
-        kh[2 * i] = (_Float16)kre[i];
-        kh[2 * i + 1] = (_Float16)kim[i];
+        kh[2 * i] = bf ? nlos::to_bf16_bits(kre[i]) : nlos::to_f16_bits(kre[i]);
+        kh[2 * i + 1] = bf ? nlos::to_bf16_bits(kim[i]) : nlos::to_f16_bits(kim[i]);
       }
       if ((e = nlos::dev_alloc((void**)&p->d_kr, nk * 4)) != hipSuccess) return cleanup(NLOS_ERR_DEVICE, "K_r", e);
       if ((e = hipMemcpy(p->d_kr, kh.data(), nk * 4, hipMemcpyHostToDevice)) != hipSuccess)
@@ -1126,7 +1131,7 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   r.chunk_i0 = p->d_chunk_i0; r.chunk_pix = p->d_chunk_pix; r.chunk_wa = p->d_chunk_wa;
   r.chunk_wb = p->d_chunk_wb; r.nchunks = p->nchunks;
   r.Nf = (int)Nf; r.Nd = (int)Nd; r.ph_stride = (int)Nfs; r.c_stride = (int)Nds;
-  r.cut_idx = p->g.cut_idx; r.kernel_fp16 = d.kernel_prec == NLOS_FP16;
+  r.cut_idx = p->g.cut_idx; r.kernel_sp = fk_sp(d.kernel_prec); r.mfma = ctx->rsd_mfma;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
   // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d]
   a = StridedArgs{};
@@ -1669,7 +1674,7 @@ nlos_status nlos_moe(nlos_ctx* ctx, const nlos_moe_plan* p, const float* d_tau, 
   r.chunk_i0 = p->rsd->d_chunk_i0; r.chunk_pix = p->rsd->d_chunk_pix; r.chunk_wa = p->rsd->d_chunk_wa;
   r.chunk_wb = p->rsd->d_chunk_wb; r.nchunks = p->rsd->nchunks;
   r.Nf = (int)Nf; r.Nd = (int)Nd; r.ph_stride = (int)Nf; r.c_stride = (int)Nd;
-  r.cut_idx = p->rsd->g.cut_idx; r.kernel_fp16 = rd.kernel_prec == NLOS_FP16;
+  r.cut_idx = p->rsd->g.cut_idx; r.kernel_sp = fk_sp(rd.kernel_prec); r.mfma = ctx->rsd_mfma;
   HIP_TRY(ctx, timed_on(ctx, s1, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s1); }));
   a = StridedArgs{};
   a.in = Cr; a.out = Dr; a.in_plane = Nd; a.in_line = Mx * Nd; a.out_plane = Nd; a.out_line = Mx * Nd;

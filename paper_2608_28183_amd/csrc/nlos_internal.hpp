@@ -90,10 +90,14 @@ struct MoePhasorArgs {
   const int* bins;
 };
 
+// One rounding to nearest even of v to binary16 / bfloat16 (host), as stored bits.
+uint16_t to_f16_bits(double v);
+uint16_t to_bf16_bits(double v);
+
 // Radial propagation over chunks of pixels that share the lower radial bin.
 struct RsdPropArgs {
   const float2* Ph;        // [npix][Nf] spectra of the padded phasor planes
-  const void* Kr;          // [Nrho][Nf][Nd] radial kernel, float2 or __half2
+  const void* Kr;          // [Nrho][Nf][Nd] radial kernel, float2 or (re, im) FP16 / BF16 pairs
   const float2* w;         // [Nf] complex frequency weights
   float2* C;               // [npix][Nd] propagated spectra
   const int* chunk_i0;     // [nchunks] lower radial bin (-1: all-zero chunk)
@@ -104,7 +108,9 @@ struct RsdPropArgs {
   int Nf, Nd;
   int ph_stride, c_stride;  // elements between the pixel rows of Ph and of C
   int cut_idx;
-  int kernel_fp16;
+  int kernel_sp;           // SP_F32, SP_F16 or SP_BF16: storage of Kr
+  int mfma;                // FP16 / BF16 kernels on the matrix cores: 0 no, 1 yes, 2 yes with
+                           // one 32-depth tile per wave
 };
 
 // stream: non-temporal loads and stores (FP32 LD_C64 -> ST_C64 only; ignored otherwise)
@@ -151,10 +157,11 @@ hipError_t launch_moe_mix(const float* fk_img, const float* rsd_img, float* img,
 
 // FP16 storage scales of the f-k intermediates from the bound B = sum |tau| t/(nt-1)
 // (nt a power of two): partials[kScaleBlocks] scratch, exps[4] = the exponents of
-// W1/W2, W3, W4, W5; l_norm = log2(Mx My Mt), l_my = log2 My, l_mx = log2 Mx.
+// W1/W2, W3, W4, W5; l_norm = log2(Mx My Mt), l_first_inv / l_second_inv = log2 of the
+// length of the first (x, Mx) and second (y, My) inverse pass.
 constexpr int kScaleBlocks = 1024;
 hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
-                            int l_norm, int l_my, int l_mx, hipStream_t s);
+                            int l_norm, int l_first_inv, int l_second_inv, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
 
 // Constant operands of the matrix-core DFT stages (mfma_fft.hpp), per context, indexed

@@ -48,6 +48,7 @@ class Request:
     future: Optional[concurrent.futures.Future] = None
     slot: int = -1
     handle: Any = None
+    ready: Any = None                # set at submit: marks the input complete on its stream
 
 
 def percentile(xs: List[float], q: float) -> float:
@@ -122,6 +123,9 @@ class Server:
     def submit(self, req: Request) -> concurrent.futures.Future:
         req.future = concurrent.futures.Future()
         req.need_bytes = int(self.ex.need_bytes(req))
+        prepare = getattr(self.ex, "prepare", None)
+        if prepare is not None:
+            prepare(req)     # in the submitting thread: sees the caller's current stream
         with self._lock:
             req.id = self._next_id
             self._next_id += 1
@@ -273,10 +277,21 @@ class GpuExecutor:
         nz = nt if req.method == "fk" else p.n_depth
         return p.ws_bytes + 4 * ny * nx * nz + 4 * ny * nx
 
+    def prepare(self, req: Request) -> None:
+        """At submit time: an event on the submitting thread's current stream, after the
+        work that produced req.tau, which the slot stream waits for before reading it."""
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.device))
+        req.ready = ev
+
     def start(self, req: Request, slot: int):
         torch = self.torch
         p = self.plan(req.method, req.shape, req.precision)
         s = self.streams[slot]
+        if req.ready is not None:
+            s.wait_event(req.ready)
+        # the input is in use on the slot stream until the reconstruction ends there
+        req.tau.record_stream(s)
         ny, nx, nt = req.shape
         nz = nt if req.method == "fk" else p.n_depth
         with torch.cuda.stream(s):

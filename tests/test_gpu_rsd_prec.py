@@ -1,0 +1,127 @@
+"""RSD with an FP16 / BF16 radial kernel: the propagation on the matrix cores.
+
+Against the FP64 oracle.  Each product term of the propagation rounds the kernel value
+K_r (at storage) and the tap-weighted phasor (to the kernel's format, after a power-of-two
+scaling that keeps it in range) once, so every term carries a relative error of at most
+2u (u = 2^-11 FP16, 2^-8 BF16) and the FP32 accumulation adds far less.  The inverse
+2D DFT is unitary up to its scale, so the same relative error bounds the field I and
+|I| in L2 when the terms do not cancel: 2u is the ceiling (9.8e-4 FP16, 7.8e-3 BF16).
+The bounds below are about 4x the errors measured at 128 x 128 x 1024 (volume FP16
+1.24e-4, BF16 9.97e-4; image 1.7e-5 and 1.4e-4) and below the ceiling.  The peak
+voxel must agree exactly.  The matrix-core path is also compared with the FP32-FMA path
+over the same stored kernel (NLOS_RSD_MFMA=0): they differ only by the rounding of the
+phasors.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import rsd as orsd
+from oracle.metrics import argmax_distance, argmax_index, rel_l2
+from paper_2608_28183_amd import runtime
+
+from gpu_util import rsd_plan_for, say, to_dev
+
+pytestmark = pytest.mark.gpu
+UNIT = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+VOL_TOL = {"fp16": 5e-4, "bf16": 4e-3}
+
+
+def context(mode=None):
+    """A context created with NLOS_RSD_MFMA = mode (None: the default, the matrix cores)."""
+    old = os.environ.pop("NLOS_RSD_MFMA", None)
+    try:
+        if mode is not None:
+            os.environ["NLOS_RSD_MFMA"] = mode
+        return runtime.Context(0)
+    finally:
+        os.environ.pop("NLOS_RSD_MFMA", None)
+        if old is not None:
+            os.environ["NLOS_RSD_MFMA"] = old
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return context()
+
+
+def run(ctx, cfg, tau, kernel_prec, pad=2, params=None):
+    plan, p = rsd_plan_for(ctx, cfg, pad=pad, kernel_prec=kernel_prec, params=params)
+    vol = torch.full((cfg.ny, cfg.nx, p.n_depth), -1.0, device="cuda")
+    img = torch.full((cfg.ny, cfg.nx), -1.0, device="cuda")
+    plan(to_dev(tau.astype(np.float32)), vol, img, plan.workspace())
+    torch.cuda.synchronize()
+    assert torch.equal(vol.amax(dim=2), img)
+    return np.moveaxis(vol.cpu().numpy().astype(np.float64), 2, 0), img.cpu().numpy().astype(np.float64), p
+
+
+def oracle(cfg, tau, p, pad=2):
+    depths = p.depth0 + p.depth_step * np.arange(p.n_depth)
+    return orsd.rsd(tau.astype(np.float64), cfg.dx, cfg.dy, cfg.bin_ps, pad, p.freq_bins, p.weights, depths,
+                    p.sigma_s, p.sigma_t, p.delta)
+
+
+def check(tag, prec, vol, img, rv, ri):
+    ev, ei = rel_l2(vol, rv), rel_l2(img, ri)
+    say(f"  {tag} {prec}: vol rel_l2 {ev:.2e}, img rel_l2 {ei:.2e}, peak distance {argmax_distance(vol, rv)}")
+    assert VOL_TOL[prec] < 2 * UNIT[prec]
+    assert ev < VOL_TOL[prec] and ei < VOL_TOL[prec]
+    assert argmax_index(vol) == argmax_index(rv)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_c1_low_precision_kernel(ctx, prec):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    vol, img, p = run(ctx, cfg, tau, prec)
+    rv, ri = oracle(cfg, tau, p)
+    check("c1", prec, vol, img, rv, ri)
+
+
+# depth counts around the 32-depth tiles, a frequency count that is not a multiple of 4,
+# pad 1, and partial pixel chunks (every grid has chunks of fewer than 64 pixels)
+@pytest.mark.parametrize("nd,pad,nfreq", [(1, 2, None), (37, 2, None), (64, 1, None), (70, 2, 7), (130, 2, 5)])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_tiles_and_edges(ctx, nd, pad, nfreq, prec):
+    cfg = scenes.small_config(16, 16, 128, bin_ps=64, n_depth=nd)
+    tau = scenes.transient(cfg, noise=True)
+    p = scenes.rsd_params(cfg)
+    if nfreq is not None:
+        p = scenes.RsdParams(p.freq_bins[:nfreq], p.weights[:nfreq], p.depth0, p.depth_step, p.n_depth,
+                             p.sigma_s, p.sigma_t, p.delta)
+    vol, img, _ = run(ctx, cfg, tau, prec, pad=pad, params=p)
+    rv, ri = oracle(cfg, tau, p, pad)
+    check(f"nd {nd} pad {pad} nf {len(p.freq_bins)}", prec, vol, img, rv, ri)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_matrix_cores_against_fma_path(prec):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    res = {}
+    for mode in ("0", "1", "2"):
+        c = context(mode)
+        res[mode] = run(c, cfg, tau, prec)[0]
+    # one and two depth tiles per wave run the same products in the same order
+    assert np.array_equal(res["1"], res["2"])
+    e = rel_l2(res["1"], res["0"])
+    say(f"  c1 {prec}: matrix cores vs FP32 FMAs over the same kernel, rel_l2 {e:.2e}")
+    assert e < 2 * UNIT[prec]
+
+
+@pytest.fixture(scope="module")
+def c3_oracle():
+    cfg = scenes.CONFIGS["c3"]
+    tau = scenes.config_transient("c3")
+    p = scenes.rsd_params(cfg)
+    return cfg, tau, p, oracle(cfg, tau, p)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_c3_full_volume_low_precision_kernel(ctx, c3_oracle, prec):
+    cfg, tau, p, (rv, ri) = c3_oracle
+    vol, img, _ = run(ctx, cfg, tau, prec)
+    check("c3 128x128x1024", prec, vol, img, rv, ri)

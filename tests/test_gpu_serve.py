@@ -32,14 +32,25 @@ def test_results_alone_equal_results_in_the_mix(lib):
     # plans first (resident), then the burst
     for r in reqs:
         ex.plan(r.method, r.shape, r.precision)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
     srv.start()
     futs = [srv.submit(r) for r in reqs]
     outs = [f.result(timeout=300) for f in futs]
     srv.stop()
+    torch.cuda.synchronize()
     st = srv.stats.summary()
     say(f"serve burst: {st}")
     assert st["completed"] == len(reqs)
     assert srv.stats.peak_bytes <= budget
+    # device memory actually held: the in-flight workspaces and outputs stay within the
+    # budget; the outputs of finished requests belong to the client on top of it
+    handed_out = sum(v.numel() * 4 + i.numel() * 4 for v, i in outs)
+    grown = torch.cuda.max_memory_allocated() - base
+    say(f"device memory growth {grown / 2**30:.2f} GiB, budget {budget / 2**30:.0f} GiB, "
+        f"results handed out {handed_out / 2**30:.2f} GiB")
+    assert grown <= budget + handed_out + (64 << 20)
     assert srv.stats.peak_inflight >= 2          # work from several requests overlapped
 
     # each request alone on one stream, the same plan

@@ -17,27 +17,39 @@ class SimExecutor:
         self.fail_ids = set(fail_ids)
         self.running = 0
         self.max_running = 0
+        self.held = 0            # bytes of the requests started and not yet finished
+        self.max_held = 0
+        self.prepared = {}       # request object id -> submitting thread
         self.order = []
         self.lock = threading.Lock()
 
     def need_bytes(self, req):
         return self.need(req)
 
+    def prepare(self, req):
+        req.ready = ("ready", threading.get_ident())
+        self.prepared[id(req)] = threading.get_ident()
+
     def start(self, req, slot):
+        # the input was marked complete at submit, in the submitting thread
+        assert req.ready is not None and id(req) in self.prepared
         if req.id in self.fail_ids:
             raise RuntimeError("injected launch failure")
         with self.lock:
             self.running += 1
             self.max_running = max(self.max_running, self.running)
+            self.held += self.need(req)
+            self.max_held = max(self.max_held, self.held)
             self.order.append(req.id)
-        return time.perf_counter() + self.duration
+        return (time.perf_counter() + self.duration, self.need(req))
 
     def done(self, handle):
-        return time.perf_counter() >= handle
+        return time.perf_counter() >= handle[0]
 
     def finish(self, req):
         with self.lock:
             self.running -= 1
+            self.held -= req.handle[1]
         return ("result", req.id)
 
 
@@ -60,16 +72,32 @@ def test_slots_bound_concurrency_and_results_arrive():
 
 
 def test_memory_budget_is_never_exceeded():
-    sizes = {0: 6, 1: 5, 2: 3, 3: 8, 4: 2, 5: 9}
-    ex = SimExecutor(need=lambda r: sizes[r.id % 6] << 30, duration=0.01)
+    # sizes in GiB by the request's first dimension; the executor counts the bytes of the
+    # requests it is actually running, independently of the scheduler's bookkeeping
+    sizes = [6, 5, 3, 8, 2, 9]
+    ex = SimExecutor(need=lambda r: sizes[r.shape[0] % 6] << 30, duration=0.01)
     srv = Server(ex, n_slots=8, hbm_budget=10 << 30).start()
-    futs = [srv.submit(Request("rsd", (8, 8, 8))) for _ in range(30)]
+    futs = [srv.submit(Request("rsd", (k % 6, 8, 8))) for k in range(30)]
     for f in futs:
         f.result(timeout=20)
     srv.stop()
-    assert srv.stats.peak_bytes <= 10 << 30
+    assert ex.max_held <= 10 << 30
+    assert ex.max_held >= 8 << 30       # the budget was actually approached
+    assert srv.stats.peak_bytes <= 10 << 30 and ex.held == 0
     assert srv.stats.completed == 30
     assert ex.order == sorted(ex.order)
+
+
+def test_inputs_are_marked_ready_in_the_submitting_thread():
+    ex = SimExecutor(duration=0.005)
+    srv = Server(ex, n_slots=2, hbm_budget=100 << 30).start()
+    reqs = [Request("fk", (8, 8, 8)) for _ in range(6)]
+    futs = [srv.submit(r) for r in reqs]
+    for f in futs:
+        f.result(timeout=10)
+    srv.stop()
+    me = threading.get_ident()
+    assert all(r.ready == ("ready", me) and ex.prepared[id(r)] == me for r in reqs)
 
 
 def test_oversize_request_is_rejected_and_failure_frees_the_slot():
