@@ -62,10 +62,10 @@ def fk_full_schedule_bytes(ny, nx, nt, pad):
         (c * ny * Mx * nt + 4 * ny * nx * nt)
 
 
-def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0, kernel_bytes=8):
+def rsd_pass_bytes(ny, nx, nt, pad, nf, nd, nrho, nchunks=0, kernel_bytes=8, data_bytes=8):
     """Algorithmic bytes of each RSD pass (frequency / depth contiguous layout)."""
     Mx, My = pad * nx, pad * ny
-    c = 8
+    c = data_bytes
     return {
         "rsd_phasor": 4 * ny * nx * nt + c * ny * nx * nf,
         "rsd_x": c * ny * nx * nf + c * ny * Mx * nf,
@@ -256,8 +256,8 @@ def main():
                     help="copy_1GiB: a plain device copy of 1 GiB, the reference that the HBM "
                          "byte counters of the other workloads are scaled by")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
-                    help="f-k: storage precision of the complex intermediates; RSD: storage of the "
-                         "radial kernel (FP16 / BF16 propagate on the matrix cores)")
+                    help="storage precision of the complex intermediates (RSD: and of the radial "
+                         "kernel, FP16 / BF16 propagating on the matrix cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
@@ -309,14 +309,18 @@ def main():
                                else scenes.transient(cfg)).to(dev)
         p = scenes.rsd_params(cfg)
         plan = runtime.RsdPlan(ctx, ny, nx, nt, cfg.dx, cfg.dy, cfg.bin_ps, cfg.pad, p.freq_bins,
-                               p.weights, p.n_depth, p.depth0, p.depth_step, kernel_prec=args.prec)
+                               p.weights, p.n_depth, p.depth0, p.depth_step, data_prec=args.prec,
+                               kernel_prec=args.prec)
         ws = plan.workspace()
         vol = torch.empty((ny, nx, p.n_depth), device=dev)
         img = torch.empty((ny, nx), device=dev)
         step = lambda: plan(tau, vol, img, ws)  # noqa: E731
         g = nlos.nlos_rsd_geometry_get(plan.desc)
         pass_bytes = rsd_pass_bytes(ny, nx, nt, cfg.pad, len(p.freq_bins), p.n_depth, g["n_rho"],
-                                    kernel_bytes=8 if args.prec == "fp32" else 4)
+                                    kernel_bytes=8 if args.prec == "fp32" else 4,
+                                    data_bytes=8 if args.prec == "fp32" else 4)
+        if args.prec == "fp16":
+            pass_bytes["rsd_scale"] = 4 * ny * nx * nt  # the bound's read of tau
         # the propagation's arithmetic: per padded pixel, frequency, depth and radial tap one
         # complex multiply-add (8 flops)
         prop_flops = 16 * (cfg.pad * ny) * (cfg.pad * nx) * len(p.freq_bins) * p.n_depth

@@ -100,7 +100,8 @@ typedef enum {
   NLOS_PASS_PHASOR_BIN = 17,   /* phasors straight from photon records */
   NLOS_PASS_MERGE = 18,        /* coherence-weighted temporal merging */
   NLOS_PASS_DDA = 19,          /* depth-dependent temporal average */
-  NLOS_PASS_COUNT = 20
+  NLOS_PASS_RSD_SCALE = 20,    /* RSD FP16 storage scales from the input bound */
+  NLOS_PASS_COUNT = 21
 } nlos_pass;
 
 /* Turns per-pass timing on (1) or off (0) for later calls on ctx. */
@@ -252,8 +253,16 @@ typedef struct {
   double depth_step_m;     /* spacing of the depth planes (m) */
   int sigma_s, sigma_t;    /* modality: (2, 0) confocal, (1, 1) non-confocal */
   double delta_m;          /* calibration offset of the optical path (m) */
-  nlos_precision data_prec;   /* storage of the complex intermediates */
-  nlos_precision kernel_prec; /* storage of the radial kernel K_r */
+  nlos_precision data_prec;   /* storage of the complex intermediates P, X, P^, C, D:
+                                 NLOS_FP32 (8-byte complex) or NLOS_FP16 / NLOS_BF16
+                                 (4-byte; needs kernel_prec == data_prec and power-of-two
+                                 pad*nx, pad*ny, nt; FP16 values are stored times exact
+                                 powers of two computed on the device from L = sum |tau|:
+                                 one for P, X, P^ and one per depth plane for C and D,
+                                 from the plan's per-depth kernel bound) */
+  nlos_precision kernel_prec; /* storage of the radial kernel K_r: NLOS_FP32, or NLOS_FP16 /
+                                 NLOS_BF16 (rounded once), whose propagation runs on the
+                                 matrix cores with FP32 accumulation */
   int vol_depth_major;        /* layout of nlos_rsd's d_vol: 0 [ny][nx][n_depth] (depth
                                  contiguous, like the time axis of the transient); 1
                                  [n_depth][ny][nx] (a stack of depth planes), written by one
@@ -273,7 +282,8 @@ typedef struct {
 /* Host-only validation: dims >= 1, pad in {1, 2}; pad*nx, pad*ny and nt each a power
  * of two in [8, 2048] or an even length in [8, 4096] with prime factors 2, 3, 5, 7, 11,
  * 13 (else NLOS_ERR_UNSUPPORTED); frequency bins in range, positive spacings, n_depth
- * in [1, 4096], sigma_s in {1, 2}. */
+ * in [1, 4096], sigma_s in {1, 2}; FP16 / BF16 data as stated at data_prec (else
+ * NLOS_ERR_UNSUPPORTED). */
 nlos_status nlos_rsd_check(const nlos_rsd_desc *desc);
 /* Host-only: the radial sampling geometry of desc. */
 nlos_status nlos_rsd_geometry_get(const nlos_rsd_desc *desc, nlos_rsd_geometry *out);
@@ -299,11 +309,14 @@ nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_plan *plan, size_t *bytes);
  *   I[d] = IDFT2(C[d]) normalised by 1/(Mx My).
  * Writes d_vol = |I| on the unpadded grid, [ny][nx][n_depth] (depth contiguous, like the
  * time axis of the transient) or, with desc->vol_depth_major, [n_depth][ny][nx], and
- * d_img[ny][nx] = max over depth; either may be NULL (not both).  Workspace as for nlos_fk. */
+ * d_img[ny][nx] = max over depth; either may be NULL (not both).  Workspace as for nlos_fk.
+ * FP16 data plans need d_tau 8-byte aligned (NLOS_ERR_INVALID_ARG otherwise). */
 nlos_status nlos_rsd(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_tau, float *d_vol,
                      float *d_img, void *d_ws, size_t ws_bytes);
 /* nlos_rsd from phasors already at the plan's frequencies: d_phasor[ny][nx][n_freq]
- * complex (float re, im; e.g. from nlos_phasor_bin with the same bins), read only. */
+ * complex (float re, im; e.g. from nlos_phasor_bin with the same bins), read only.  FP32
+ * data plans only (NLOS_ERR_UNSUPPORTED otherwise: the FP16 scales are bounds of the
+ * transient). */
 nlos_status nlos_rsd_from_phasors(nlos_ctx *ctx, const nlos_rsd_plan *plan, const float *d_phasor, float *d_vol,
                                   float *d_img, void *d_ws, size_t ws_bytes);
 

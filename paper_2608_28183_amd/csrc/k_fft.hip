@@ -58,7 +58,7 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
                                 (colok ? col : 0) + (long long)p * a.in_line;
     load_first_stage<S>(raw, p, a.n_in, colok, ST_::zero(),
                         [&](int n) { return ST_::raw(in, (long long)(n - p) * a.in_line); });
-    const int e = SP == SP_F16 ? -*a.e_in : 0;
+    const int e = SP == SP_F16 ? -a.e_in[a.e_per_col && colok ? col : 0] : 0;
 #pragma unroll
     for (int j = 0; j < E_; ++j) {
       v[j] = ST_::cvt(raw[j]);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
 
   auto idx = [&](int n) { return n * C::LDS_W + c; };
   if constexpr (ST == ST_C64 && SP != SP_F32) {
-    const int e = SP == SP_F16 ? *a.e_out : 0;
+    const int e = SP == SP_F16 ? a.e_out[a.e_per_col && colok ? col : 0] : 0;
     fft_run<S, INV, false>(v, p, lds, idx, tw, [&](int n, float2 val) {
       if (colok && n < a.n_out)
         ST_::st(static_cast<typename ST_::T*>(a.out), plane * a.out_plane + (long long)n * a.out_line + col,
@@ -179,17 +179,26 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   float2* my = lds + (NEED_LDS ? l * C::LSTRIDE : 0);
   auto idx = [&](int n) { return swz(n); };
   if constexpr (ST == CS_BINS) {
-    // natural-order spectrum into LDS, then gather the requested bins
+    // natural-order spectrum into LDS, then gather the requested bins (four-byte output
+    // for SP_F16 / SP_BF16, FP16 times 2^(*e_out))
     auto store = [&](int n, float2 val) { my[swz(n)] = val; };
     fft_run<S, INV, true>(v, p, my, idx, tw, store);
     __syncthreads();
     const long long line0 = (long long)blockIdx.x * C::L;
+    const int eo = SP == SP_F16 ? *a.e_out : 0;
     for (int k = tid; k < C::L * a.nbins; k += C::THREADS) {
       const int ll = k / a.nbins;
       const int f = k % a.nbins;
       const long long ln = line0 + ll;
-      if (ln < a.nlines)
-        static_cast<float2*>(a.out)[ln * a.out_line + f] = lds[ll * C::LSTRIDE + swz(a.bins[f])];
+      if (ln < a.nlines) {
+        const float2 val = lds[ll * C::LSTRIDE + swz(a.bins[f])];
+        if constexpr (SP == SP_F32) {
+          static_cast<float2*>(a.out)[ln * a.out_line + f] = val;
+        } else {
+          using SO = Stor<SP>;
+          SO::st(static_cast<typename SO::T*>(a.out), ln * a.out_line + f, SP == SP_F16 ? ldexp2(val, eo) : val);
+        }
+      }
     }
   } else if constexpr (ST == CS_ABS2_MAX) {
     // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]
@@ -279,6 +288,15 @@ hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs
   if (sp == SP_BF16 && ld == LD_C64 && st == ST_C64)
     return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_BF16>(n, a, nplanes, tw, s)
                    : launch_strided_inv<false, LD_C64, ST_C64, SP_BF16>(n, a, nplanes, tw, s);
+  // four-byte input, FP32 output (the last RSD pass: |I| or the complex field)
+  if (sp == SP_F16 && inverse && ld == LD_C64 && st == ST_ABS_IMG)
+    return launch_strided_inv<true, LD_C64, ST_ABS_IMG, SP_F16>(n, a, nplanes, tw, s);
+  if (sp == SP_BF16 && inverse && ld == LD_C64 && st == ST_ABS_IMG)
+    return launch_strided_inv<true, LD_C64, ST_ABS_IMG, SP_BF16>(n, a, nplanes, tw, s);
+  if (sp == SP_F16 && inverse && ld == LD_C64 && st == ST_C64_SCALED)
+    return launch_strided_inv<true, LD_C64, ST_C64_SCALED, SP_F16>(n, a, nplanes, tw, s);
+  if (sp == SP_BF16 && inverse && ld == LD_C64 && st == ST_C64_SCALED)
+    return launch_strided_inv<true, LD_C64, ST_C64_SCALED, SP_BF16>(n, a, nplanes, tw, s);
   if (sp != SP_F32) return hipErrorInvalidValue;
   if (!inverse && ld == LD_TAU_SCALED && st == ST_C64)
     return launch_strided_inv<false, LD_TAU_SCALED, ST_C64>(n, a, nplanes, tw, s);
@@ -332,6 +350,11 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16>(n, a, tw, s);
   if (sp == SP_BF16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16>(n, a, tw, s);
+  // the RSD phasor pass with four-byte output
+  if (sp == SP_F16 && !inverse && ld == CL_REAL && st == CS_BINS)
+    return launch_contig_inv<false, CL_REAL, CS_BINS, SP_F16>(n, a, tw, s);
+  if (sp == SP_BF16 && !inverse && ld == CL_REAL && st == CS_BINS)
+    return launch_contig_inv<false, CL_REAL, CS_BINS, SP_BF16>(n, a, tw, s);
   if (sp != SP_F32) return hipErrorInvalidValue;
   if (!inverse && ld == CL_REAL && st == CS_BINS)
     return launch_contig_inv<false, CL_REAL, CS_BINS>(n, a, tw, s);

@@ -13,6 +13,8 @@
 // element is produced by one lane in a fixed frequency order.
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "mfma_fft.hpp"
 #include "nlos_internal.hpp"
 
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
     // unused slots have wa = wb = 0 and read pixel 0's row
     const float wa = a.chunk_wa[g * kGroupPix + lane];
     const float wb = a.chunk_wb[g * kGroupPix + lane];
-    const float2* __restrict__ ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
+    const float2* __restrict__ ph = static_cast<const float2*>(a.Ph) + (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
     long long o0 = (long long)i0 * Nf * Nd + d0;
     long long o1 = (long long)i1 * Nf * Nd + d0;
     if (d0 + kDepths <= Nd) {
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
     }
   }
   if (pix < 0) return;
-  float2* out = a.C + (long long)pix * a.c_stride + d0;
+  float2* out = static_cast<float2*>(a.C) + (long long)pix * a.c_stride + d0;
 #pragma unroll
   for (int j = 0; j < kDepths; ++j)
     if (d0 + j < Nd) out[j] = acc[j];
@@ -129,9 +131,12 @@ __global__ __launch_bounds__(256) void rsd_propagate(RsdPropArgs a) {
 // the imaginary part.  A is rounded to the kernel's format after scaling by a power of two
 // 2^e chosen per chunk from the largest |w_f P^| (wa | wb) of its pixels (a first pass
 // over their rows), so that every component stays below 2^14; the FP32 result is
-// multiplied by 2^-e.  A wave takes one chunk and DT 32-depth tiles.
+// multiplied by 2^-e.  A wave takes one chunk and DT 32-depth tiles.  DATA4: P^ and C are
+// stored in the kernel's four-byte format too (FP16 P^ times 2^e_ph, FP16 C at depth d
+// written times 2^e_c[d]); the chunk scale is then chosen on the stored values and the
+// exponents are folded into one final ldexp.
 
-template <int SP, int DT>
+template <int SP, int DT, bool DATA4>
 __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
   using M = Mfma<SP>;
   const int lane = threadIdx.x & 63;
@@ -156,23 +161,35 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
       for (int o = 0; o < 2; ++o)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][q][o][v] = 0.f;
-  float inv_scale = 1.f;
+  int out_exp = 0;  // C = acc 2^out_exp (before its own storage scale)
   if (i0 >= 0) {
     const int i1 = i0 + 1 < a.cut_idx ? i0 + 1 : a.cut_idx;
     // pass 1: the largest component of w_f P^ times the larger tap weight
     float m = 0.f;
     {
       const float tw = fmaxf(a.chunk_wa[g * kGroupPix + lane], a.chunk_wb[g * kGroupPix + lane]);
-      const float2* ph = a.Ph + (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
+      const long long row = (long long)(pix >= 0 ? pix : 0) * a.ph_stride;
       constexpr int U = 16;  // loads in flight per lane (unconditional, clamped indices:
                              // a repeated last frequency does not change the maximum)
       for (int f0 = 0; f0 < Nf; f0 += U) {
         float2 p[U], wf[U];
+        if constexpr (DATA4) {
+          unsigned int raw[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int f = min(f0 + u, Nf - 1);
-          p[u] = ph[f];
-          wf[u] = a.w[f];
+          for (int u = 0; u < U; ++u) {
+            const int f = min(f0 + u, Nf - 1);
+            raw[u] = static_cast<const unsigned int*>(a.Ph)[row + f];
+            wf[u] = a.w[f];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) p[u] = M::unpack(raw[u]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int f = min(f0 + u, Nf - 1);
+            p[u] = static_cast<const float2*>(a.Ph)[row + f];
+            wf[u] = a.w[f];
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -188,12 +205,19 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
     if (m > 0.f) (void)frexpf(m, &ex);  // m < 2^ex
     // clamped so that the scaled tap weights (<= 1) and 2^-e stay finite normal floats
     const int e = min(max(14 - ex, -100), 100);
-    inv_scale = ldexpf(1.f, -e);
+    out_exp = -e;
     const float wa0 = ldexpf(a.chunk_wa[g * kGroupPix + c32], e), wb0 = ldexpf(a.chunk_wb[g * kGroupPix + c32], e);
     const float wa1 = ldexpf(a.chunk_wa[g * kGroupPix + 32 + c32], e);
     const float wb1 = ldexpf(a.chunk_wb[g * kGroupPix + 32 + c32], e);
-    const float2* ph0 = a.Ph + (long long)(pr0 >= 0 ? pr0 : 0) * a.ph_stride;
-    const float2* ph1 = a.Ph + (long long)(pr1 >= 0 ? pr1 : 0) * a.ph_stride;
+    const long long row0 = (long long)(pr0 >= 0 ? pr0 : 0) * a.ph_stride;
+    const long long row1 = (long long)(pr1 >= 0 ? pr1 : 0) * a.ph_stride;
+    // the phasors of rows 0 and 1 at frequency f, loaded as stored
+    using PRaw = typename std::conditional<DATA4, unsigned int, float2>::type;
+    auto ldp = [&](long long row, int f) { return static_cast<const PRaw*>(a.Ph)[row + f]; };
+    auto cvp = [&](PRaw r) {
+      if constexpr (DATA4) return M::unpack(r);
+      else return r;
+    };
     const unsigned int* kr = static_cast<const unsigned int*>(a.Kr);
     const long long k0 = (long long)i0 * Nf * Nd, k1 = (long long)i1 * Nf * Nd;
     // one K step: this lane's frequencies fa = f0, fb = f0 + 1.  Every load is
@@ -202,7 +226,8 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
     // A entries are then 0, whatever kernel value it meets), and a depth beyond Nd only
     // feeds output columns that are never stored.
     struct Step {
-      float2 wfa, wfb, pa0, pb0, pa1, pb1;
+      float2 wfa, wfb;
+      PRaw pa0, pb0, pa1, pb1;
       float ma, mb;
       unsigned int kv[DT][4];  // [depth tile][K0a, K1a, K0b, K1b]
     };
@@ -213,10 +238,10 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
       t.mb = f0 + 1 < Nf ? 1.f : 0.f;
       t.wfa = a.w[fa];
       t.wfb = a.w[fb];
-      t.pa0 = ph0[fa];
-      t.pb0 = ph0[fb];
-      t.pa1 = ph1[fa];
-      t.pb1 = ph1[fb];
+      t.pa0 = ldp(row0, fa);
+      t.pb0 = ldp(row0, fb);
+      t.pa1 = ldp(row1, fa);
+      t.pb1 = ldp(row1, fb);
 #pragma unroll
       for (int q = 0; q < DT; ++q) {
         const int d = min(d0 + 32 * q + c32, Nd - 1);
@@ -230,7 +255,8 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
     auto cm = [](float2 p, float2 wf) { return make_float2(p.x * wf.x - p.y * wf.y, p.x * wf.y + p.y * wf.x); };
     auto step = [&](const Step& t) {
       const float2 wa_ = make_float2(t.wfa.x * t.ma, t.wfa.y * t.ma), wb_ = make_float2(t.wfb.x * t.mb, t.wfb.y * t.mb);
-      const float2 za0 = cm(t.pa0, wa_), zb0 = cm(t.pb0, wb_), za1 = cm(t.pa1, wa_), zb1 = cm(t.pb1, wb_);
+      const float2 za0 = cm(cvp(t.pa0), wa_), zb0 = cm(cvp(t.pb0), wb_), za1 = cm(cvp(t.pa1), wa_),
+                   zb1 = cm(cvp(t.pb1), wb_);
       mf_u4 A[2];
       A[0] = mf_u4{M::pack(za0.x * wa0, za0.y * wa0), M::pack(za0.x * wb0, za0.y * wb0),
                    M::pack(zb0.x * wa0, zb0.y * wa0), M::pack(zb0.x * wb0, zb0.y * wb0)};
@@ -267,6 +293,14 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
     }
   }
   // D lane layout: rows 8(v/4) + 4 hl + v%4 of the tile, column c32
+  int qexp[DT];  // final exponent per depth tile column: the chunk scale, and for FP16
+                 // data the stored P^ scale (undone) and C's storage scale at that depth
+#pragma unroll
+  for (int q = 0; q < DT; ++q) {
+    const int d = min(d0 + 32 * q + c32, Nd - 1);
+    qexp[q] = out_exp;
+    if constexpr (DATA4 && SP == SP_F16) qexp[q] += a.e_c[d] - a.e_ph[0];
+  }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -276,14 +310,86 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
 #pragma unroll
       for (int q = 0; q < DT; ++q) {
         const int d = d0 + 32 * q + c32;
-        if (pp >= 0 && d < Nd)
-          a.C[(long long)pp * a.c_stride + d] =
-              make_float2(acc[r][q][0][v] * inv_scale, acc[r][q][1][v] * inv_scale);
+        if (pp >= 0 && d < Nd) {
+          const float re = ldexpf(acc[r][q][0][v], qexp[q]), im = ldexpf(acc[r][q][1][v], qexp[q]);
+          const long long o = (long long)pp * a.c_stride + d;
+          if constexpr (DATA4) static_cast<unsigned int*>(a.C)[o] = M::pack(re, im);
+          else static_cast<float2*>(a.C)[o] = make_float2(re, im);
+        }
       }
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP16 storage scales of the RSD intermediates
+// ---------------------------------------------------------------------------
+//
+// L = sum |tau| bounds every phasor |P[f]| (a DFT of one pixel's line), and so also the x
+// and y DFTs of the padded phasor planes (sums over pixels).  The propagated plane at
+// depth d is bounded by L kappa_d with kappa_d = sum_f |w_f| max_i |K_r[i][f][d]| (the
+// tap weights are at most 1), and its unnormalised y-IFFT by My L kappa_d.  Each is stored
+// times 2^(14 - k) with bound = f 2^k, f in [0.5, 1), so stored magnitudes stay below
+// 2^14: one exponent for P, X and P^, one per depth plane for C and for D.  L is summed in
+// a fixed order, so the scales, and the results, are deterministic.
+
+__global__ __launch_bounds__(256) void rsd_l1_partial(const float2* __restrict__ tau, long long n2,
+                                                      float* __restrict__ partials) {
+  __shared__ float red[4];
+  float acc = 0.f;
+  const long long stride = (long long)gridDim.x * 256;
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n2; i += 4 * stride) {  // four loads in flight per thread
+    const float2 v0 = tau[i], v1 = tau[i + stride], v2 = tau[i + 2 * stride], v3 = tau[i + 3 * stride];
+    acc += ((fabsf(v0.x) + fabsf(v0.y)) + (fabsf(v1.x) + fabsf(v1.y))) +
+           ((fabsf(v2.x) + fabsf(v2.y)) + (fabsf(v3.x) + fabsf(v3.y)));
+  }
+  for (; i < n2; i += stride) acc += fabsf(tau[i].x) + fabsf(tau[i].y);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ __forceinline__ int rsd_storage_exponent(float bound) {
+  if (!(bound > 0.f) || !(bound <= 3.0e38f)) return 0;
+  int k = 0;
+  (void)frexpf(bound, &k);
+  return min(max(14 - k, -120), 120);
+}
+
+__global__ __launch_bounds__(256) void rsd_scale_exponents(const float* __restrict__ partials, int np,
+                                                           const float* __restrict__ kappa, int nd, int l_my,
+                                                           int* __restrict__ exps) {
+  __shared__ float red[4];
+  float acc = 0.f;
+  for (int j = threadIdx.x; j < np; j += 256) acc += partials[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  const float L = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) exps[0] = rsd_storage_exponent(L);
+  for (int d = threadIdx.x; d < nd; d += 256) {
+    const int ec = rsd_storage_exponent(L * kappa[d]);
+    exps[1 + d] = ec;
+    exps[1 + nd + d] = ec - l_my;
+  }
+}
+
+hipError_t launch_rsd_scales(const float* tau, long long n, float* partials, const float* kappa, int nd, int l_my,
+                             int* exps, hipStream_t s) {
+  if (n % 2 != 0 || nd < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rsd_l1_partial, dim3(kScaleBlocks), dim3(256), 0, s, reinterpret_cast<const float2*>(tau),
+                     n / 2, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rsd_scale_exponents, dim3(1), dim3(256), 0, s, partials, kScaleBlocks, kappa, nd, l_my, exps);
+  return hipGetLastError();
+}
+
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
+  if (a.data_sp != SP_F32 && (a.data_sp != a.kernel_sp || !a.mfma)) return hipErrorInvalidValue;
   if (a.mfma && (a.kernel_sp == SP_F16 || a.kernel_sp == SP_BF16)) {
     // depth tiles per wave: two unless a.mfma asks for one or one covers every depth
     const int dt = (a.mfma == 2 || a.Nd <= 32) ? 1 : 2;
@@ -292,13 +398,16 @@ hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
+    const bool d4 = a.data_sp != SP_F32;
+#define NLOS_PROP(SPV, DTV, D4V) hipLaunchKernelGGL((rsd_propagate_mfma<SPV, DTV, D4V>), grid, dim3(256), 0, s, a)
     if (a.kernel_sp == SP_F16) {
-      if (dt == 1) hipLaunchKernelGGL((rsd_propagate_mfma<SP_F16, 1>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((rsd_propagate_mfma<SP_F16, 2>), grid, dim3(256), 0, s, a);
+      if (d4) { if (dt == 1) NLOS_PROP(SP_F16, 1, true); else NLOS_PROP(SP_F16, 2, true); }
+      else { if (dt == 1) NLOS_PROP(SP_F16, 1, false); else NLOS_PROP(SP_F16, 2, false); }
     } else {
-      if (dt == 1) hipLaunchKernelGGL((rsd_propagate_mfma<SP_BF16, 1>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((rsd_propagate_mfma<SP_BF16, 2>), grid, dim3(256), 0, s, a);
+      if (d4) { if (dt == 1) NLOS_PROP(SP_BF16, 1, true); else NLOS_PROP(SP_BF16, 2, true); }
+      else { if (dt == 1) NLOS_PROP(SP_BF16, 1, false); else NLOS_PROP(SP_BF16, 2, false); }
     }
+#undef NLOS_PROP
     return hipGetLastError();
   }
   const long long nds = (a.Nd + kDepths - 1) / kDepths;

@@ -196,7 +196,8 @@ struct nlos_rsd_plan {
   int device = 0;
   int Mx = 0, My = 0;
   nlos::RsdGeometry g{};
-  void* d_kr = nullptr;       // [Nrho][Nf][Nd] float2 or __half2
+  void* d_kr = nullptr;       // [Nrho][Nf][Nd] float2 or (re, im) FP16 / BF16 pairs
+  float* d_kappa = nullptr;   // [Nd] sum_f |w_f| max_i |K_r[i][f][d]| (four-byte data: scales)
   float2* d_w = nullptr;      // [Nf]
   int* d_bins = nullptr;      // [Nf]
   int* d_chunk_i0 = nullptr;  // pixel chunks sharing a radial bin (rsd_build_chunks)
@@ -267,7 +268,7 @@ static hipError_t timed_on(nlos_ctx* ctx, hipStream_t stream, int pass, F launch
 static const char* const kPassNames[NLOS_PASS_COUNT] = {
     "fill", "bin", "fk_x", "fk_y", "fk_column", "fk_yi", "fk_xi",
     "rsd_phasor", "rsd_x", "rsd_y", "rsd_propagate", "rsd_yi", "rsd_xi", "fk_zi", "fk_scale",
-    "moe_phasor", "moe_mix", "phasor_bin", "merge", "dda"};
+    "moe_phasor", "moe_mix", "phasor_bin", "merge", "dda", "rsd_scale"};
 
 extern "C" {
 
@@ -858,11 +859,16 @@ nlos_status nlos_fk_noalloc(nlos_ctx* ctx, const nlos_fk_plan* p, const float* d
 //   B: x-FFT output [ny][Mx][Nfs], later the propagated spectra C [My][Mx][Nds]
 //   E: y-FFT output P^ [My][Mx][Nfs]
 struct RsdLayout {
-  size_t b_off, e_off, total;
+  size_t b_off, e_off, total;  // complex elements of es bytes
   size_t nfs, nds;  // row strides (elements) of the frequency and depth contiguous arrays
+  size_t es;        // 8 (FP32 data) or 4 (FP16 / BF16 data)
+  size_t scale_off; // bytes: FP16 scale scratch (kScaleBlocks partial sums, 1 + 2 Nd exponents)
+  size_t bytes;     // the whole workspace
 };
 // Rows of Nf frequencies or Nd depths are padded to a multiple of 16 complex values (128
-// bytes), so that the column tiles of the strided passes cover whole cache lines.
+// bytes at FP32), so that the column tiles of the strided passes cover whole cache lines.
+// The last pass writes |I| (float) depth contiguous into region B when the caller asks
+// for a depth-major volume: ny nx Nd floats fit in My Mx Nds elements of either size.
 static RsdLayout rsd_layout(const nlos_rsd_desc* d) {
   const size_t Mx = (size_t)d->pad * d->nx, My = (size_t)d->pad * d->ny;
   auto up = [](size_t n) { return (n + 31) / 32 * 32; };
@@ -871,11 +877,15 @@ static RsdLayout rsd_layout(const nlos_rsd_desc* d) {
   RsdLayout L;
   L.nfs = nf;
   L.nds = nd;
+  L.es = d->data_prec == NLOS_FP32 ? 8 : 4;
   const size_t a = up(std::max(ny * nx * nf, ny * Mx * nd));
   const size_t b = up(std::max(ny * Mx * nf, My * Mx * nd));
   L.b_off = a;
   L.e_off = a + b;
   L.total = a + b + My * Mx * nf;
+  L.scale_off = (L.total * L.es + 255) / 256 * 256;
+  L.bytes = d->data_prec == NLOS_FP16 ? L.scale_off + 4 * (size_t)nlos::kScaleBlocks + 4 * (1 + 2 * (size_t)d->n_depth)
+                                      : L.total * L.es;
   return L;
 }
 
@@ -922,7 +932,15 @@ nlos_status nlos_rsd_check(const nlos_rsd_desc* d) {
                   d->freq_bin[f]);
   for (int f = 0; f < 2 * d->n_freq; ++f)
     if (!std::isfinite(d->w[f])) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: w is not finite");
-  if (d->data_prec != NLOS_FP32) return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: only FP32 data is built");
+  if (d->data_prec != NLOS_FP32) {
+    // four-byte intermediates: the power-of-two passes and the matrix-core propagation
+    // with a kernel stored in the same format
+    if (d->kernel_prec != d->data_prec)
+      return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: FP16 / BF16 data needs kernel_prec equal to data_prec");
+    for (long long m : {p * d->nx, p * d->ny, (long long)d->nt})
+      if (!is_pow2_in(m, 8, 2048))
+        return fail(nullptr, NLOS_ERR_UNSUPPORTED, "rsd: FP16 / BF16 data needs power-of-two pad*nx, pad*ny and nt");
+  }
   return NLOS_OK;
 }
 
@@ -968,13 +986,13 @@ nlos_status nlos_rsd_desc_workspace_bytes(const nlos_rsd_desc* d, size_t* bytes)
   nlos_status st = nlos_rsd_check(d);
   if (st != NLOS_OK) return st;
   if (!bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "rsd: bytes is NULL");
-  *bytes = rsd_layout(d).total * 8;
+  *bytes = rsd_layout(d).bytes;
   return NLOS_OK;
 }
 
 nlos_status nlos_rsd_workspace_bytes(const nlos_rsd_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(nullptr, NLOS_ERR_INVALID_ARG, "nlos_rsd_workspace_bytes: NULL argument");
-  *bytes = rsd_layout(&p->d).total * 8;
+  *bytes = rsd_layout(&p->d).bytes;
   return NLOS_OK;
 }
 
@@ -982,6 +1000,7 @@ nlos_status nlos_rsd_plan_destroy(nlos_rsd_plan* p) {
   if (!p) return NLOS_OK;
   (void)hipSetDevice(p->device);
   if (p->d_kr) (void)hipFree(p->d_kr);
+  if (p->d_kappa) (void)hipFree(p->d_kappa);
   if (p->d_chunk_i0) (void)hipFree(p->d_chunk_i0);
   if (p->d_chunk_pix) (void)hipFree(p->d_chunk_pix);
   if (p->d_chunk_wa) (void)hipFree(p->d_chunk_wa);
@@ -1041,6 +1060,29 @@ nlos_status nlos_rsd_plan_create(nlos_ctx* ctx, const nlos_rsd_desc* d, nlos_rsd
       if ((e = hipMemcpy(p->d_kr, kf.data(), nk * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(NLOS_ERR_DEVICE, "K_r upload", e);
     }
+    if (d->data_prec != NLOS_FP32) {
+      // kappa_d = sum_f |w_f| max_i |K_r[i][f][d]|: with L = sum |tau| it bounds the
+      // propagated plane at depth d (FP16 storage scales)
+      const int Nf = d->n_freq, Nd = d->n_depth;
+      const size_t nrho = nk / ((size_t)Nf * Nd);
+      std::vector<float> kappa(Nd);
+      for (int dd = 0; dd < Nd; ++dd) {
+        double sum = 0.0;
+        for (int f = 0; f < Nf; ++f) {
+          double mx = 0.0;
+          for (size_t i = 0; i < nrho; ++i) {
+            const size_t o = (i * Nf + f) * Nd + dd;
+            mx = std::max(mx, std::hypot(kre[o], kim[o]));
+          }
+          sum += std::hypot((double)d->w[2 * f], (double)d->w[2 * f + 1]) * mx;
+        }
+        kappa[dd] = (float)sum;
+      }
+      if ((e = nlos::dev_alloc((void**)&p->d_kappa, Nd * sizeof(float))) != hipSuccess)
+        return cleanup(NLOS_ERR_DEVICE, "kappa", e);
+      if ((e = hipMemcpy(p->d_kappa, kappa.data(), Nd * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(NLOS_ERR_DEVICE, "kappa upload", e);
+    }
     p->nchunks = ch.count();
     auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
       hipError_t r = nlos::dev_alloc((void**)dst, bytes);
@@ -1084,46 +1126,60 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   const long long nx = d.nx, ny = d.ny, nt = d.nt, Mx = p->Mx, My = p->My;
   const long long Nf = d.n_freq, Nd = d.n_depth;
   const RsdLayout L = rsd_layout(&d);
-  float2* base = static_cast<float2*>(ws);
+  const int sp = fk_sp(d.data_prec);  // storage of the complex intermediates
+  char* base = static_cast<char*>(ws);
+  const size_t es = L.es;
   // frequency rows hold Nf values in a stride of Nfs, depth rows Nd in Nds
   const long long Nfs = (long long)L.nfs, Nds = (long long)L.nds;
-  float2* P = base;                 // [ny][nx][Nfs]
-  float2* X = base + L.b_off;       // [ny][Mx][Nfs]
-  float2* Ph = base + L.e_off;      // [My][Mx][Nfs]
-  float2* C = base + L.b_off;       // [My][Mx][Nds]
-  float2* D = base;                 // [ny][Mx][Nds]
+  void* P = base;                   // [ny][nx][Nfs]
+  void* X = base + L.b_off * es;    // [ny][Mx][Nfs]
+  void* Ph = base + L.e_off * es;   // [My][Mx][Nfs]
+  void* C = base + L.b_off * es;    // [My][Mx][Nds]
+  void* D = base;                   // [ny][Mx][Nds]
   const float2* tw = ctx->d_tw;
   if (d_img)
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
       return nlos::launch_fill_u32(reinterpret_cast<uint32_t*>(d_img), (size_t)nx * ny, 0u, s);
     }));
+  // FP16 storage exponents: [0] P, X, P^; [1 + d] C at depth d; [1 + Nd + d] D at depth d
+  int* ex = nullptr;
+  if (sp == nlos::SP_F16) {
+    float* partials = reinterpret_cast<float*>(base + L.scale_off);
+    ex = reinterpret_cast<int*>(base + L.scale_off + 4 * (size_t)nlos::kScaleBlocks);
+    HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_SCALE, [&] {
+      return nlos::launch_rsd_scales(d_tau, ny * nx * nt, partials, p->d_kappa, (int)Nd, ilog2((int)My), ex, s);
+    }));
+  }
+  const int* e_pc = ex ? ex + 1 : nullptr;            // per depth: C
+  const int* e_pd = ex ? ex + 1 + Nd : nullptr;       // per depth: D
 
   // 1. phasors: t-FFT of each pixel, bins k_f -> P[y][x][f] (or the caller's phasors)
   if (!d_phasor) {
     ContigArgs c{};
     c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.out_line = Nfs; c.n_in = (int)nt;
-    c.n_out = (int)nt; c.bins = p->d_bins; c.nbins = (int)Nf;
+    c.n_out = (int)nt; c.bins = p->d_bins; c.nbins = (int)Nf; c.e_out = ex;
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] {
       return p->gen_t ? nlos::launch_gen_contig(p->gt, false, nlos::CL_REAL, nlos::CS_BINS, c, s)
-                      : nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s);
+                      : nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s, sp);
     }));
   }
   // 2. x-FFT of the top-left padded planes: lines along x, columns f
   StridedArgs a{};
   const long long Pin = d_phasor ? Nf : Nfs;  // the caller's phasors are [ny][nx][Nf]
-  a.in = d_phasor ? d_phasor : P; a.out = X; a.in_plane = nx * Pin; a.in_line = Pin; a.out_plane = Mx * Nfs;
-  a.out_line = Nfs; a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
+  a.in = d_phasor ? static_cast<const void*>(d_phasor) : P; a.out = X; a.in_plane = nx * Pin; a.in_line = Pin;
+  a.out_plane = Mx * Nfs; a.out_line = Nfs; a.ncols = (int)Nf; a.n_in = (int)nx; a.n_out = (int)Mx;
+  a.e_in = ex; a.e_out = ex;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_X, [&] {
     return p->gen_x ? nlos::launch_gen_strided(p->gx, false, nlos::ST_C64, a, (int)ny, s)
-                    : nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s);
+                    : nlos::launch_strided((int)Mx, false, nlos::LD_C64, nlos::ST_C64, a, (int)ny, tw, s, sp);
   }));
   // 3. y-FFT: planes kx, lines along y -> P^[ky][kx][f]
   a = StridedArgs{};
   a.in = X; a.out = Ph; a.in_plane = Nfs; a.in_line = Mx * Nfs; a.out_plane = Nfs; a.out_line = Mx * Nfs;
-  a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My;
+  a.ncols = (int)Nf; a.n_in = (int)ny; a.n_out = (int)My; a.e_in = ex; a.e_out = ex;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_Y, [&] {
     return p->gen_y ? nlos::launch_gen_strided(p->gy, false, nlos::ST_C64, a, (int)Mx, s)
-                    : nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s);
+                    : nlos::launch_strided((int)My, false, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp);
   }));
   // 4. radial propagation over pixel chunks: P^ -> C[pix][d]
   nlos::RsdPropArgs r{};
@@ -1131,37 +1187,40 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
   r.chunk_i0 = p->d_chunk_i0; r.chunk_pix = p->d_chunk_pix; r.chunk_wa = p->d_chunk_wa;
   r.chunk_wb = p->d_chunk_wb; r.nchunks = p->nchunks;
   r.Nf = (int)Nf; r.Nd = (int)Nd; r.ph_stride = (int)Nfs; r.c_stride = (int)Nds;
-  r.cut_idx = p->g.cut_idx; r.kernel_sp = fk_sp(d.kernel_prec); r.mfma = ctx->rsd_mfma;
+  r.cut_idx = p->g.cut_idx; r.kernel_sp = fk_sp(d.kernel_prec);
+  // four-byte data exist only on the matrix cores
+  r.mfma = sp != nlos::SP_F32 && ctx->rsd_mfma == 0 ? 1 : ctx->rsd_mfma;
+  r.data_sp = sp; r.e_ph = ex; r.e_c = e_pc;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PROPAGATE, [&] { return nlos::launch_rsd_propagate(r, s); }));
-  // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d]
+  // 5. y-IFFT per depth column, keep y < ny: C -> D[y][kx][d] (FP16: per-depth exponents)
   a = StridedArgs{};
   a.in = C; a.out = D; a.in_plane = Nds; a.in_line = Mx * Nds; a.out_plane = Nds; a.out_line = Mx * Nds;
-  a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny;
+  a.ncols = (int)Nd; a.n_in = (int)My; a.n_out = (int)ny; a.e_in = e_pc; a.e_out = e_pd; a.e_per_col = 1;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_YI, [&] {
     return p->gen_y ? nlos::launch_gen_strided(p->gy, true, nlos::ST_C64, a, (int)Mx, s)
-                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s);
+                    : nlos::launch_strided((int)My, true, nlos::LD_C64, nlos::ST_C64, a, (int)Mx, tw, s, sp);
   }));
   // 6. x-IFFT, keep x < nx, |I| / (Mx My) -> vol[y][x][d], max over depth -> img
   a = StridedArgs{};
   a.in = D; a.out = d_vol; a.in_plane = Mx * Nds; a.in_line = Nds; a.out_plane = nx * Nd; a.out_line = Nd;
-  a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx;
+  a.ncols = (int)Nd; a.n_in = (int)Mx; a.n_out = (int)nx; a.e_in = e_pd; a.e_per_col = 1;
   a.oscale = (float)(1.0 / ((double)Mx * (double)My)); a.img = d_img; a.img_plane = nx;
   if (d_field) {  // the complex field I itself
     a.out = d_field; a.img = nullptr;
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] {
       return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_C64_SCALED, a, (int)ny, s)
-                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64_SCALED, a, (int)ny, tw, s);
+                      : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_C64_SCALED, a, (int)ny, tw, s, sp);
     }));
     return NLOS_OK;
   }
   // depth-major volume: |I| lands depth contiguous in region B (C is dead), then one
   // transpose pass writes d_vol[n_depth][ny][nx]
   const bool depth_major = d.vol_depth_major && d_vol != nullptr;
-  float* vtmp = reinterpret_cast<float*>(base + L.b_off);
+  float* vtmp = reinterpret_cast<float*>(base + L.b_off * es);
   if (depth_major) a.out = vtmp;
   HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_XI, [&] {
     return p->gen_x ? nlos::launch_gen_strided(p->gx, true, nlos::ST_ABS_IMG, a, (int)ny, s)
-                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s);
+                    : nlos::launch_strided((int)Mx, true, nlos::LD_C64, nlos::ST_ABS_IMG, a, (int)ny, tw, s, sp);
   }));
   if (depth_major)
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_FILL, [&] {
@@ -1174,12 +1233,14 @@ nlos_status nlos_rsd(nlos_ctx* ctx, const nlos_rsd_plan* p, const float* d_tau, 
                      void* d_ws, size_t ws_bytes) {
   if (!ctx || !p) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: ctx or plan is NULL");
   if (!d_tau) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_tau is NULL");
+  if (p->d.data_prec == NLOS_FP16 && reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_tau must be 8-byte aligned for FP16 data");
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd: plan of another device");
   const RsdLayout L = rsd_layout(&p->d);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.bytes, &ws);
   if (st != NLOS_OK) return st;
   return rsd_run(ctx, p, ctx->stream, d_tau, d_vol, d_img, ws);
 }
@@ -1192,10 +1253,13 @@ nlos_status nlos_rsd_from_phasors(nlos_ctx* ctx, const nlos_rsd_plan* p, const f
     return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: d_phasor must be 8-byte aligned");
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_from_phasors: plan of another device");
+  if (p->d.data_prec != NLOS_FP32)
+    return fail(ctx, NLOS_ERR_UNSUPPORTED, "nlos_rsd_from_phasors: FP32 data plans only (the FP16 scales come from "
+                                           "the transient)");
   const RsdLayout L = rsd_layout(&p->d);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.total * 8, &ws);
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, L.bytes, &ws);
   if (st != NLOS_OK) return st;
   return rsd_run(ctx, p, ctx->stream, nullptr, d_vol, d_img, ws, reinterpret_cast<const float2*>(d_phasor));
 }
@@ -1222,9 +1286,11 @@ nlos_status nlos_rsd_complex(nlos_ctx* ctx, const nlos_rsd_plan* p, const float*
   if (reinterpret_cast<uintptr_t>(d_field) % 8 != 0)
     return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: d_field must be 8-byte aligned");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: plan of another device");
+  if (p->d.data_prec == NLOS_FP16 && reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_complex: d_tau must be 8-byte aligned for FP16 data");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).total * 8, &ws);
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).bytes, &ws);
   if (st != NLOS_OK) return st;
   return rsd_run(ctx, p, ctx->stream, d_tau, nullptr, nullptr, ws, nullptr, reinterpret_cast<float2*>(d_field));
 }
@@ -1304,11 +1370,13 @@ nlos_status nlos_rsd_graph_create(nlos_ctx* ctx, const nlos_rsd_plan* p, const f
                                   float* d_img, void* d_ws, size_t ws_bytes, nlos_graph** out) {
   if (!ctx || !p || !out) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: NULL argument");
   if (!d_tau || !d_ws) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: d_tau and d_ws are required");
+  if (p->d.data_prec == NLOS_FP16 && reinterpret_cast<uintptr_t>(d_tau) % 8 != 0)
+    return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: d_tau must be 8-byte aligned for FP16 data");
   if (!d_vol && !d_img) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: d_vol and d_img are both NULL");
   if (p->device != ctx->device) return fail(ctx, NLOS_ERR_INVALID_ARG, "nlos_rsd_graph_create: plan of another device");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   void* ws = nullptr;
-  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).total * 8, &ws);
+  nlos_status st = get_workspace(ctx, d_ws, ws_bytes, rsd_layout(&p->d).bytes, &ws);
   if (st != NLOS_OK) return st;
   return capture_graph(
       ctx, "nlos_rsd_graph_create", [&](hipStream_t cs) { return rsd_run(ctx, p, cs, d_tau, d_vol, d_img, ws); }, out);
@@ -1550,7 +1618,7 @@ static MoeLayout moe_layout(const nlos_fk_desc* fk, const nlos_rsd_desc* rsd) {
   MoeLayout L;
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   L.rsd_off = up(fk_layout(fk).bytes);
-  L.img_off = L.rsd_off + up(rsd_layout(rsd).total * 8);
+  L.img_off = L.rsd_off + up(rsd_layout(rsd).bytes);
   L.bytes = L.img_off + up(2 * sizeof(float) * (size_t)fk->nx * fk->ny) + 256;  // + 3 maxima
   return L;
 }

@@ -32,9 +32,11 @@ struct StridedArgs {
   float* img;          // ST_ABS*_IMG: img[plane * img_plane + n] = max over columns (may be null)
   long long img_plane;
   // four-byte storage (SP_F16 / SP_BF16): an FP16 input holds value * 2^(*e_in) and an
-  // FP16 output is written as value * 2^(*e_out); BF16 is unscaled
+  // FP16 output is written as value * 2^(*e_out); BF16 is unscaled.  e_per_col: one
+  // exponent per column instead, e_in[col] / e_out[col] (per-plane scales)
   const int* e_in;
   const int* e_out;
+  int e_per_col;
 };
 
 // Lines along the contiguous axis: line `ln` is in[ln * in_line + n], n < n_in.
@@ -50,6 +52,7 @@ struct ContigArgs {
   const int* bins;     // CS_BINS: out[ln * out_line + f] = X[bins[f]], f < nbins
   int nbins;
   const int* e_in;     // FP16 input: holds value * 2^(*e_in)
+  const int* e_out;    // CS_BINS with FP16 output: written as value * 2^(*e_out)
 };
 
 // f-k pass 1: tau[ny][nx][nt] (float) -> half spectrum out[ny][Mx/2 + 1][nt] with
@@ -96,10 +99,11 @@ uint16_t to_bf16_bits(double v);
 
 // Radial propagation over chunks of pixels that share the lower radial bin.
 struct RsdPropArgs {
-  const float2* Ph;        // [npix][Nf] spectra of the padded phasor planes
+  const void* Ph;          // [npix][Nf] spectra of the padded phasor planes (float2, or
+                           // four-byte pairs when data_sp != SP_F32)
   const void* Kr;          // [Nrho][Nf][Nd] radial kernel, float2 or (re, im) FP16 / BF16 pairs
   const float2* w;         // [Nf] complex frequency weights
-  float2* C;               // [npix][Nd] propagated spectra
+  void* C;                 // [npix][Nd] propagated spectra (float2 or four-byte pairs)
   const int* chunk_i0;     // [nchunks] lower radial bin (-1: all-zero chunk)
   const int* chunk_pix;    // [nchunks][64] pixel index or -1
   const float* chunk_wa;   // [nchunks][64] a (1 - alpha), 0 in unused slots
@@ -109,6 +113,11 @@ struct RsdPropArgs {
   int ph_stride, c_stride;  // elements between the pixel rows of Ph and of C
   int cut_idx;
   int kernel_sp;           // SP_F32, SP_F16 or SP_BF16: storage of Kr
+  int data_sp;             // storage of Ph and C (four-byte forms: matrix cores, data_sp ==
+                           // kernel_sp); FP16 Ph holds value * 2^e_ph[0], FP16 C[.][d] is
+                           // written as value * 2^e_c[d]
+  const int* e_ph;
+  const int* e_c;
   int mfma;                // FP16 / BF16 kernels on the matrix cores: 0 no, 1 yes, 2 yes with
                            // one 32-depth tile per wave
 };
@@ -163,6 +172,11 @@ constexpr int kScaleBlocks = 1024;
 hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partials, int* exps,
                             int l_norm, int l_first_inv, int l_second_inv, hipStream_t s);
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s);
+// FP16 storage scales of the RSD intermediates from L = sum |tau| (n values, n even):
+// exps[0] for P, X and P^ (bound L), exps[1 + d] for C at depth d (bound L kappa[d]) and
+// exps[1 + nd + d] for D (bound My L kappa[d], l_my = log2 My); partials[kScaleBlocks].
+hipError_t launch_rsd_scales(const float* tau, long long n, float* partials, const float* kappa, int nd, int l_my,
+                             int* exps, hipStream_t s);
 
 // Constant operands of the matrix-core DFT stages (mfma_fft.hpp), per context, indexed
 // [inverse][scaled by 1/R][0 binary16, 1 bfloat16]; 64 lanes x 16 bytes per operand.

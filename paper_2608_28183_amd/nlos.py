@@ -210,7 +210,7 @@ def nlos_last_error(ctx: Optional[int] = None) -> str:
     return lib().nlos_last_error(ctx).decode(errors="replace")
 
 
-NLOS_PASS_COUNT = 20
+NLOS_PASS_COUNT = 21
 
 
 def nlos_pass_name(p: int) -> str:

@@ -225,10 +225,11 @@ class Server:
 
 
 def rsd_precisions(precision: str) -> Tuple[str, str]:
-    """(data, kernel) storage of an RSD request: the reduced-precision form stores the
-    radial kernel K_r in FP16 (accumulated in FP64, rounded once on store).  An f-k
-    request's precision is the storage of its complex intermediates (fp32, fp16, bf16)."""
-    return ("fp32", "fp32") if precision == "fp32" else ("fp32", "fp16")
+    """(data, kernel) storage of an RSD request: the reduced-precision forms store the
+    complex intermediates and the radial kernel K_r (accumulated in FP64, rounded once on
+    store) in FP16 or BF16, and propagate on the matrix cores.  An f-k request's
+    precision is the storage of its complex intermediates (fp32, fp16, bf16)."""
+    return (precision, precision)
 
 
 class GpuExecutor:

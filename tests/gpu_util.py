@@ -32,11 +32,11 @@ def run_fk(ctx, tau, wall_w=1.0, wall_h=1.0, bin_ps=32.0, pad=2, prec="fp32", wi
     return vol.cpu().numpy().astype(np.float64), img.cpu().numpy().astype(np.float64)
 
 
-def rsd_plan_for(ctx, cfg, pad=2, n_depth=None, kernel_prec="fp32", params=None):
+def rsd_plan_for(ctx, cfg, pad=2, n_depth=None, kernel_prec="fp32", params=None, data_prec="fp32"):
     p = scenes.rsd_params(cfg, n_depth) if params is None else params
     plan = runtime.RsdPlan(ctx, cfg.ny, cfg.nx, cfg.nt, cfg.dx, cfg.dy, cfg.bin_ps, pad,
                            p.freq_bins, p.weights, p.n_depth, p.depth0, p.depth_step,
-                           p.sigma_s, p.sigma_t, p.delta, "fp32", kernel_prec)
+                           p.sigma_s, p.sigma_t, p.delta, data_prec, kernel_prec)
     return plan, p
 
 

@@ -315,3 +315,27 @@ def test_dda_default_weights_validation():
     for nd, w in [(0, 2), (2, 0), (2, 65)]:
         assert nlos.lib().nlos_dda_default_weights(nd, w, buf) == nlos.NLOS_ERR_INVALID_ARG
     assert nlos.lib().nlos_dda_default_weights(2, 2, None) == nlos.NLOS_ERR_INVALID_ARG
+
+
+def test_rsd_reduced_precision_data_rules_and_workspace():
+    cfg = scenes.CONFIGS["c1"]
+    args = (32, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5, 9, 13], [1, 1, 1], 40, 0.2, 0.01)
+    for prec in ("fp16", "bf16"):
+        ok = nlos.RsdDesc(*args, data_prec=prec, kernel_prec=prec)
+        assert nlos.nlos_rsd_check(ok) == nlos.NLOS_OK
+        # the kernel must be stored in the same format
+        for kp in ("fp32", "fp16" if prec == "bf16" else "bf16"):
+            bad = nlos.RsdDesc(*args, data_prec=prec, kernel_prec=kp)
+            assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED
+        # power-of-two grids only
+        bad = nlos.RsdDesc(30, 32, 256, cfg.dx, cfg.dy, 32.0, 2, [5], [1], 8, 0.2, 0.01, data_prec=prec,
+                           kernel_prec=prec)
+        assert nlos.nlos_rsd_check(bad) == nlos.NLOS_ERR_UNSUPPORTED
+    # FP32 data with a BF16 kernel is accepted (matrix-core propagation)
+    assert nlos.nlos_rsd_check(nlos.RsdDesc(*args, kernel_prec="bf16")) == nlos.NLOS_OK
+    # four-byte elements: about half the FP32 workspace; FP16 adds its scale scratch
+    w32 = nlos.nlos_rsd_desc_workspace_bytes(nlos.RsdDesc(*args))
+    wb = nlos.nlos_rsd_desc_workspace_bytes(nlos.RsdDesc(*args, data_prec="bf16", kernel_prec="bf16"))
+    wh = nlos.nlos_rsd_desc_workspace_bytes(nlos.RsdDesc(*args, data_prec="fp16", kernel_prec="fp16"))
+    assert wb == w32 // 2
+    assert wh >= wb + 4 * 1024 + 4 * (1 + 2 * 40) and wh - wb < 8192

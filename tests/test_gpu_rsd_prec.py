@@ -48,8 +48,8 @@ def ctx(lib):
     return context()
 
 
-def run(ctx, cfg, tau, kernel_prec, pad=2, params=None):
-    plan, p = rsd_plan_for(ctx, cfg, pad=pad, kernel_prec=kernel_prec, params=params)
+def run(ctx, cfg, tau, kernel_prec, pad=2, params=None, data_prec="fp32"):
+    plan, p = rsd_plan_for(ctx, cfg, pad=pad, kernel_prec=kernel_prec, params=params, data_prec=data_prec)
     vol = torch.full((cfg.ny, cfg.nx, p.n_depth), -1.0, device="cuda")
     img = torch.full((cfg.ny, cfg.nx), -1.0, device="cuda")
     plan(to_dev(tau.astype(np.float32)), vol, img, plan.workspace())
@@ -125,3 +125,75 @@ def test_rsd_c3_full_volume_low_precision_kernel(ctx, c3_oracle, prec):
     cfg, tau, p, (rv, ri) = c3_oracle
     vol, img, _ = run(ctx, cfg, tau, prec)
     check("c3 128x128x1024", prec, vol, img, rv, ri)
+
+
+# ---------------------------------------------------------------------------
+# FP16 / BF16 intermediates (P, X, P^, C, D stored at four bytes)
+# ---------------------------------------------------------------------------
+#
+# Besides the two roundings of every product term, each of the five stored intermediates
+# is rounded once, to a relative error of at most u per element (FP16 with exact power-of-
+# two scales: one for P, X and P^, one per depth plane for C and D, from bounds, so no
+# plane is pushed into subnormals).  The transforms are unitary up to scale, so the
+# ceiling is about 10u in relative L2 (4.9e-3 FP16, 3.9e-2 BF16); the bounds are about 4x
+# the errors measured at 128 x 128 x 1024 (volume FP16 2.3e-4, BF16 1.9e-3; image 8.2e-5
+# and 7.2e-4; strongest planes 3.7e-4 and 3.0e-3).  Each depth plane that carries at least a tenth
+# of the strongest plane's norm is checked on its own; nearly empty planes (where the
+# scene's return cancels but the rounding errors of the shared spectrum P^ do not) are
+# reported, not bounded.
+DATA_TOL = {"fp16": 1e-3, "bf16": 8e-3}
+
+
+def check_data(tag, prec, vol, img, rv, ri):
+    ev, ei = rel_l2(vol, rv), rel_l2(img, ri)
+    norms = np.sqrt(np.sum(rv.reshape(rv.shape[0], -1) ** 2, axis=1))
+    errs = np.array([rel_l2(vol[d], rv[d]) if norms[d] > 0 else 0.0 for d in range(vol.shape[0])])
+    strong = norms >= 0.1 * norms.max()
+    say(f"  {tag} data {prec}: vol rel_l2 {ev:.2e}, img rel_l2 {ei:.2e}, worst strong depth plane "
+        f"{errs[strong].max():.2e} ({strong.sum()} planes), worst plane {errs.max():.2e}, "
+        f"peak distance {argmax_distance(vol, rv)}")
+    assert DATA_TOL[prec] < 10 * UNIT[prec]
+    assert ev < DATA_TOL[prec] and ei < DATA_TOL[prec]
+    assert errs[strong].max() < 2 * DATA_TOL[prec]
+    assert argmax_distance(vol, rv) <= 1
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_c1_low_precision_data(ctx, prec):
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1")
+    vol, img, p = run(ctx, cfg, tau, prec, data_prec=prec)
+    rv, ri = oracle(cfg, tau, p)
+    check_data("c1", prec, vol, img, rv, ri)
+
+
+@pytest.mark.parametrize("nd,pad,nfreq", [(1, 2, None), (37, 2, None), (64, 1, None), (130, 2, 5)])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_low_precision_data_edges(ctx, nd, pad, nfreq, prec):
+    cfg = scenes.small_config(16, 16, 128, bin_ps=64, n_depth=nd)
+    tau = scenes.transient(cfg, noise=True)
+    p = scenes.rsd_params(cfg)
+    if nfreq is not None:
+        p = scenes.RsdParams(p.freq_bins[:nfreq], p.weights[:nfreq], p.depth0, p.depth_step, p.n_depth,
+                             p.sigma_s, p.sigma_t, p.delta)
+    vol, img, _ = run(ctx, cfg, tau, prec, pad=pad, params=p, data_prec=prec)
+    rv, ri = oracle(cfg, tau, p, pad)
+    check_data(f"nd {nd} pad {pad} nf {len(p.freq_bins)}", prec, vol, img, rv, ri)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_low_precision_data_power_of_two_equivariance(ctx, prec):
+    """The storage scales are exact powers of two from bounds of the input: an input
+    scaled by 2^-20 gives the volume scaled by 2^-20, bit for bit."""
+    cfg = scenes.CONFIGS["c1"]
+    tau = scenes.config_transient("c1").astype(np.float32)
+    v1, i1, _ = run(ctx, cfg, tau, prec, data_prec=prec)
+    v2, i2, _ = run(ctx, cfg, np.ldexp(tau, -20), prec, data_prec=prec)
+    assert np.array_equal(np.ldexp(v1, -20), v2) and np.array_equal(np.ldexp(i1, -20), i2)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rsd_c3_full_volume_low_precision_data(ctx, c3_oracle, prec):
+    cfg, tau, p, (rv, ri) = c3_oracle
+    vol, img, _ = run(ctx, cfg, tau, prec, data_prec=prec)
+    check_data("c3 128x128x1024", prec, vol, img, rv, ri)
