@@ -530,7 +530,11 @@ def main():
             # DFT stages on the matrix cores): volumes/s, per-call latency and accuracy
             precision_path = {}
             for pr in ("fp16", "bf16"):
-                pp = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad, pr)
+                try:
+                    pp = runtime.FkPlan(ctx, ny, nx, nt, cfg.wall_w, cfg.wall_h, cfg.bin_ps, cfg.pad, pr)
+                except nlos.NlosError as e:  # e.g. mixed-radix grids: FP32 only
+                    precision_path[pr] = {"unsupported": str(e)}
+                    continue
                 pws = pp.workspace()
                 pstep = lambda: pp(tau, vol, img, pws)  # noqa: E731
                 for _ in range(args.warmup):

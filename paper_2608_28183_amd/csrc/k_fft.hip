@@ -240,14 +240,15 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
 
 // (samples per thread, columns per block) of the strided passes, from timing sweeps at
 // 512-point lines (256x256x512 f-k): forward y pass E=16 T=16, inverse passes E=8 T=16;
-// 256-point lines use 32 columns (256-byte rows).  With four-byte storage the passes
-// double their columns so that a row segment stays 128 bytes (a whole cache line:
-// 64-byte segments fetch every line twice).
+// 256-point lines use 32 columns (256-byte rows).  With four-byte storage the 512-point
+// passes double their columns so that a row segment stays 128 bytes (a whole cache line:
+// 64-byte segments fetch every line twice); 256-point lines keep 32 columns, already
+// 128 bytes at four bytes, since 64 would need 128 KB of LDS per block (one block per CU).
 template <int N, bool INV, int LD, int ST, int SP = SP_F32>
 struct StridedTune {
   static constexpr bool WIDE = SP != SP_F32;
   static constexpr int E = (N == 512) ? (INV && !WIDE ? 8 : 16) : default_e(N);
-  static constexpr int T = (N == 512) ? (WIDE ? 32 : 16) : (N == 256 ? (WIDE ? 64 : 32) : default_t(N));
+  static constexpr int T = (N == 512) ? (WIDE ? 32 : 16) : (N == 256 ? 32 : default_t(N));
 };
 
 template <int N, bool INV, int LD, int ST, int SP = SP_F32, bool NT = false,
