@@ -171,7 +171,7 @@ def serve_bench(n_requests=2000, rate_hz=50.0, n_slots=4, budget_gib=24, seed=50
         "arrival_rate_hz": rate_hz, "requests": n_requests, "slots": n_slots,
         "saturation_requests": n_saturation,
         "mix": "shapes uniform over 64x64x512, 128x128x1024, 256x256x512; f-k/RSD 50/50; "
-               "fp16 = FP16 f-k intermediates, FP16 RSD kernel",
+               "fp16 = FP16 f-k intermediates, FP16 RSD intermediates and kernel",
         "fp32": one_run(("fp32",), rate_hz, budget_gib, n_requests),
         "fp16": one_run(("fp16",), rate_hz, budget_gib, n_requests),
         "fp32_fp16_mixed": one_run(("fp32", "fp16"), rate_hz, budget_gib, n_requests),
