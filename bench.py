@@ -507,8 +507,10 @@ def main():
         # the propagation is a contraction: priced against the arithmetic peak it runs on
         # (matrix cores for FP16 / BF16 kernels, FP32 FMAs otherwise), bytes kept beside
         tflops = prop_flops / (avg_ms[dom] * 1e-3) / 1e12
+        on_fma = os.environ.get("NLOS_RSD_MFMA", "1") == "0"
+        # FP32 matrix cores and FP32 vector FMAs share the published 157.3 TFLOP/s
         peak = MFMA_F16_PEAK_TFLOPS if args.prec != "fp32" else F32_VALU_PEAK_TFLOPS
-        roofline = {"bound": "mfma" if args.prec != "fp32" else "alu", "kernel": dom,
+        roofline = {"bound": "alu" if on_fma else "mfma", "kernel": dom,
                     "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(tflops / peak, 4), "traffic": traffic, "algorithmic_flops": prop_flops,
                     "avg_ms": round(avg_ms[dom], 4), "hbm_GBps": round(achieved, 1),

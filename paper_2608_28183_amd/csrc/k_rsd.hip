@@ -320,6 +320,113 @@ __global__ __launch_bounds__(256) void rsd_propagate_mfma(RsdPropArgs a) {
     }
 }
 
+// FP32 kernels on the matrix cores: the same product on v_mfma_f32_32x32x2f32 (FP32
+// operands, FP32 accumulation).  A K step is one (frequency, tap): lane l holds part
+// l/32 (re or im) of the tap-weighted phasor of its row, and the kernel value of its depth
+// column as (re, -im) for the real part of the output and (im, re) for the imaginary part,
+// the half l/32 selecting the entry.  A wave takes one chunk and DT 32-depth tiles; the
+// loads of four frequencies ahead are in flight (unconditional, clamped indices as above).
+typedef float rsd_f16v __attribute__((ext_vector_type(16)));
+
+template <int DT>
+__global__ __launch_bounds__(256) void rsd_propagate_mfma32(RsdPropArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int hl = lane >> 5, c32 = lane & 31;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nds = (a.Nd + 32 * DT - 1) / (32 * DT);
+  const long long w = (long long)blockIdx.x * kWavesPerBlock + wib;
+  if (w >= a.nchunks * nds) return;
+  const long long g = w / nds;
+  const int d0 = (int)(w % nds) * 32 * DT;
+  const int Nf = a.Nf, Nd = a.Nd;
+  const int i0 = a.chunk_i0[g];
+  const int pix = a.chunk_pix[g * kGroupPix + lane];
+  const int pr0 = a.chunk_pix[g * kGroupPix + c32], pr1 = a.chunk_pix[g * kGroupPix + 32 + c32];
+  rsd_f16v acc[2][DT][2];  // [row tile][depth tile][re | im]
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < DT; ++q)
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[r][q][o][v] = 0.f;
+  if (i0 >= 0) {
+    const int i1 = i0 + 1 < a.cut_idx ? i0 + 1 : a.cut_idx;
+    const float wa0 = a.chunk_wa[g * kGroupPix + c32], wb0 = a.chunk_wb[g * kGroupPix + c32];
+    const float wa1 = a.chunk_wa[g * kGroupPix + 32 + c32], wb1 = a.chunk_wb[g * kGroupPix + 32 + c32];
+    const float2* ph = static_cast<const float2*>(a.Ph);
+    const long long row0 = (long long)(pr0 >= 0 ? pr0 : 0) * a.ph_stride;
+    const long long row1 = (long long)(pr1 >= 0 ? pr1 : 0) * a.ph_stride;
+    const float2* kr = static_cast<const float2*>(a.Kr);
+    const long long k0 = (long long)i0 * Nf * Nd, k1 = (long long)i1 * Nf * Nd;
+    struct Step {
+      float2 wf, p0, p1;
+      float m;
+      float2 kv[DT][2];  // [depth tile][tap]
+    };
+    auto load = [&](int f) {
+      Step t;
+      const int fc = min(f, Nf - 1);
+      t.m = f < Nf ? 1.f : 0.f;
+      t.wf = a.w[fc];
+      t.p0 = ph[row0 + fc];
+      t.p1 = ph[row1 + fc];
+#pragma unroll
+      for (int q = 0; q < DT; ++q) {
+        const int d = min(d0 + 32 * q + c32, Nd - 1);
+        t.kv[q][0] = kr[k0 + (long long)fc * Nd + d];
+        t.kv[q][1] = kr[k1 + (long long)fc * Nd + d];
+      }
+      return t;
+    };
+    auto step = [&](const Step& t) {
+      const float2 wf = make_float2(t.wf.x * t.m, t.wf.y * t.m);
+      const float2 z0 = make_float2(t.p0.x * wf.x - t.p0.y * wf.y, t.p0.x * wf.y + t.p0.y * wf.x);
+      const float2 z1 = make_float2(t.p1.x * wf.x - t.p1.y * wf.y, t.p1.x * wf.y + t.p1.y * wf.x);
+      const float c0 = hl ? z0.y : z0.x, c1 = hl ? z1.y : z1.x;
+      const float A[2][2] = {{wa0 * c0, wb0 * c0}, {wa1 * c1, wb1 * c1}};  // [row tile][tap]
+#pragma unroll
+      for (int q = 0; q < DT; ++q)
+#pragma unroll
+        for (int tap = 0; tap < 2; ++tap) {
+          const float2 K = t.kv[q][tap];
+          const float bre = hl ? -K.y : K.x, bim = hl ? K.x : K.y;
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            acc[r][q][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[r][tap], bre, acc[r][q][0], 0, 0, 0);
+            acc[r][q][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[r][tap], bim, acc[r][q][1], 0, 0, 0);
+          }
+        }
+    };
+    Step b0 = load(0), b1 = load(1), b2 = load(2), b3 = load(3);
+    for (int f0 = 0; f0 < Nf; f0 += 4) {
+      step(b0);
+      b0 = load(f0 + 4);
+      if (f0 + 1 < Nf) step(b1);
+      b1 = load(f0 + 5);
+      if (f0 + 2 < Nf) step(b2);
+      b2 = load(f0 + 6);
+      if (f0 + 3 < Nf) step(b3);
+      b3 = load(f0 + 7);
+    }
+  }
+  // D lane layout: rows 8(v/4) + 4 hl + v%4 of the tile, column c32
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 32 * r + 8 * (v >> 2) + 4 * hl + (v & 3);
+      const int pp = __shfl(pix, row, 64);
+#pragma unroll
+      for (int q = 0; q < DT; ++q) {
+        const int d = d0 + 32 * q + c32;
+        if (pp >= 0 && d < Nd)
+          static_cast<float2*>(a.C)[(long long)pp * a.c_stride + d] = make_float2(acc[r][q][0][v], acc[r][q][1][v]);
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP16 storage scales of the RSD intermediates
 // ---------------------------------------------------------------------------
@@ -391,7 +498,8 @@ hipError_t launch_rsd_scales(const float* tau, long long n, float* partials, con
 hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
   if (a.data_sp != SP_F32 && (a.data_sp != a.kernel_sp || !a.mfma)) return hipErrorInvalidValue;
   if (a.mfma && (a.kernel_sp == SP_F16 || a.kernel_sp == SP_BF16)) {
-    // depth tiles per wave: two unless a.mfma asks for one or one covers every depth
+    // FP16 / BF16: two depth tiles per wave by default (0.079 against 0.114 ms with one);
+    // a.mfma == 2 asks for the other tiling
     const int dt = (a.mfma == 2 || a.Nd <= 32) ? 1 : 2;
     const long long waves = a.nchunks * ((a.Nd + 32 * dt - 1) / (32 * dt));
     const long long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -408,6 +516,18 @@ hipError_t launch_rsd_propagate(const RsdPropArgs& a, hipStream_t s) {
       else { if (dt == 1) NLOS_PROP(SP_BF16, 1, false); else NLOS_PROP(SP_BF16, 2, false); }
     }
 #undef NLOS_PROP
+    return hipGetLastError();
+  }
+  if (a.mfma && a.kernel_sp == SP_F32) {
+    // FP32: one depth tile per wave by default (two waves per SIMD: 0.133 against 0.165 ms
+    // with two tiles at 128 x 128 x 1024, 64 depths); a.mfma == 2 asks for the other tiling
+    const int dt = (a.mfma == 2 && a.Nd > 32) ? 2 : 1;
+    const long long waves = a.nchunks * ((a.Nd + 32 * dt - 1) / (32 * dt));
+    const long long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (dt == 1) hipLaunchKernelGGL(rsd_propagate_mfma32<1>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(rsd_propagate_mfma32<2>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
   }
   const long long nds = (a.Nd + kDepths - 1) / kDepths;

@@ -173,8 +173,8 @@ struct nlos_ctx {
   void* d_mfma = nullptr;             // matrix-core DFT operands (FP64-built)
   nlos::MfmaTables mt{};
   bool mfma = true;                   // four-byte f-k passes on the matrix cores
-  int rsd_mfma = 1;                   // FP16 / BF16 radial kernels on the matrix cores (0 no; 2 one
-                                      // depth tile per wave)
+  int rsd_mfma = 1;                   // RSD propagation on the matrix cores (0 no: FP32 FMAs; 2 the
+                                      // other depth tiling)
 };
 
 struct nlos_fk_plan {

@@ -118,8 +118,9 @@ struct RsdPropArgs {
                            // written as value * 2^e_c[d]
   const int* e_ph;
   const int* e_c;
-  int mfma;                // FP16 / BF16 kernels on the matrix cores: 0 no, 1 yes, 2 yes with
-                           // one 32-depth tile per wave
+  int mfma;                // propagation on the matrix cores: 0 no (FP32 FMAs), 1 yes, 2 yes
+                           // with the other depth tiling (FP32: two 32-depth tiles per wave,
+                           // FP16 / BF16: one)
 };
 
 // stream: non-temporal loads and stores (FP32 LD_C64 -> ST_C64 only; ignored otherwise)

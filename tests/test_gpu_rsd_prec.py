@@ -1,4 +1,5 @@
-"""RSD with an FP16 / BF16 radial kernel: the propagation on the matrix cores.
+"""RSD propagation on the matrix cores (FP32, FP16 and BF16 radial kernels), and RSD with
+FP16 / BF16 intermediates.
 
 Against the FP64 oracle.  Each product term of the propagation rounds the kernel value
 K_r (at storage) and the tap-weighted phasor (to the kernel's format, after a power-of-two
@@ -97,7 +98,7 @@ def test_rsd_tiles_and_edges(ctx, nd, pad, nfreq, prec):
     check(f"nd {nd} pad {pad} nf {len(p.freq_bins)}", prec, vol, img, rv, ri)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 def test_rsd_matrix_cores_against_fma_path(prec):
     cfg = scenes.CONFIGS["c1"]
     tau = scenes.config_transient("c1")
@@ -105,11 +106,12 @@ def test_rsd_matrix_cores_against_fma_path(prec):
     for mode in ("0", "1", "2"):
         c = context(mode)
         res[mode] = run(c, cfg, tau, prec)[0]
-    # one and two depth tiles per wave run the same products in the same order
+    # the two depth tilings (modes 1 and 2) run the same products in the same order
     assert np.array_equal(res["1"], res["2"])
     e = rel_l2(res["1"], res["0"])
     say(f"  c1 {prec}: matrix cores vs FP32 FMAs over the same kernel, rel_l2 {e:.2e}")
-    assert e < 2 * UNIT[prec]
+    # FP32 kernels: both forms are FP32 products summed in FP32, in different orders
+    assert e < (1e-6 if prec == "fp32" else 2 * UNIT[prec])
 
 
 @pytest.fixture(scope="module")
