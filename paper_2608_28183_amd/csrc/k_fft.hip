@@ -134,7 +134,8 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   const long long line = (long long)blockIdx.x * C::L + l;
   const bool lineok = line < a.nlines;
   float2 v[E];
-  if constexpr (SP == SP_F32 || LD == CL_REAL) {
+  if constexpr (SP == SP_F32 || LD == CL_REAL || LD == CL_REAL_PAIR) {
+    const bool oddok = LD == CL_REAL_PAIR && 2 * line + 1 < a.nreal;  // the pair's second line
     static_for<E / S::R0>([&](auto b_) {
       static_for<S::R0>([&](auto r_) {
         constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
@@ -142,11 +143,14 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
         float2 x = make_float2(0.f, 0.f);
         constexpr bool ZERO = HALF && (b * (N / E) + r * (N / S::R0) >= N / 2);  // n >= N/2 for every p
         if (!ZERO && lineok && n < (HALF ? N / 2 : a.n_in)) {
-          const long long i = line * a.in_line + n;
           if constexpr (LD == CL_REAL) {
-            x.x = static_cast<const float*>(a.in)[i];
+            x.x = static_cast<const float*>(a.in)[line * a.in_line + n];
+          } else if constexpr (LD == CL_REAL_PAIR) {
+            const float* f = static_cast<const float*>(a.in);
+            x.x = f[2 * line * a.in_line + n];
+            if (oddok) x.y = f[(2 * line + 1) * a.in_line + n];
           } else {
-            x = static_cast<const float2*>(a.in)[i];
+            x = static_cast<const float2*>(a.in)[line * a.in_line + n];
           }
         }
         v[b * S::R0 + r] = x;
@@ -186,17 +190,29 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
     __syncthreads();
     const long long line0 = (long long)blockIdx.x * C::L;
     const int eo = SP == SP_F16 ? *a.e_out : 0;
+    auto put = [&](long long row, int f, float2 val) {
+      if constexpr (SP == SP_F32) {
+        static_cast<float2*>(a.out)[row * a.out_line + f] = val;
+      } else {
+        using SO = Stor<SP>;
+        SO::st(static_cast<typename SO::T*>(a.out), row * a.out_line + f, SP == SP_F16 ? ldexp2(val, eo) : val);
+      }
+    };
     for (int k = tid; k < C::L * a.nbins; k += C::THREADS) {
       const int ll = k / a.nbins;
       const int f = k % a.nbins;
       const long long ln = line0 + ll;
       if (ln < a.nlines) {
-        const float2 val = lds[ll * C::LSTRIDE + swz(a.bins[f])];
-        if constexpr (SP == SP_F32) {
-          static_cast<float2*>(a.out)[ln * a.out_line + f] = val;
+        const int bin = a.bins[f];
+        const float2 z = lds[ll * C::LSTRIDE + swz(bin)];
+        if constexpr (LD == CL_REAL_PAIR) {
+          // Z = X_a + i X_b for real lines a, b: X_a[k] = (Z[k] + conj Z[N-k]) / 2,
+          // X_b[k] = (Z[k] - conj Z[N-k]) / 2i
+          const float2 zm = lds[ll * C::LSTRIDE + swz((N - bin) & (N - 1))];
+          put(2 * ln, f, make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)));
+          if (2 * ln + 1 < a.nreal) put(2 * ln + 1, f, make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x)));
         } else {
-          using SO = Stor<SP>;
-          SO::st(static_cast<typename SO::T*>(a.out), ln * a.out_line + f, SP == SP_F16 ? ldexp2(val, eo) : val);
+          put(ln, f, z);
         }
       }
     }
@@ -351,7 +367,12 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16>(n, a, tw, s);
   if (sp == SP_BF16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)
     return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16>(n, a, tw, s);
-  // the RSD phasor pass with four-byte output
+  // the RSD phasor pass: two real pixel lines per complex line, FP32 or four-byte output
+  if (!inverse && ld == CL_REAL_PAIR && st == CS_BINS) {
+    if (sp == SP_F16) return launch_contig_inv<false, CL_REAL_PAIR, CS_BINS, SP_F16>(n, a, tw, s);
+    if (sp == SP_BF16) return launch_contig_inv<false, CL_REAL_PAIR, CS_BINS, SP_BF16>(n, a, tw, s);
+    return launch_contig_inv<false, CL_REAL_PAIR, CS_BINS, SP_F32>(n, a, tw, s);
+  }
   if (sp == SP_F16 && !inverse && ld == CL_REAL && st == CS_BINS)
     return launch_contig_inv<false, CL_REAL, CS_BINS, SP_F16>(n, a, tw, s);
   if (sp == SP_BF16 && !inverse && ld == CL_REAL && st == CS_BINS)

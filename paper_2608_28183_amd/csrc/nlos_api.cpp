@@ -1158,9 +1158,13 @@ static nlos_status rsd_run(nlos_ctx* ctx, const nlos_rsd_plan* p, hipStream_t s,
     ContigArgs c{};
     c.in = d_tau; c.out = P; c.nlines = ny * nx; c.in_line = nt; c.out_line = Nfs; c.n_in = (int)nt;
     c.n_out = (int)nt; c.bins = p->d_bins; c.nbins = (int)Nf; c.e_out = ex;
+    if (!p->gen_t) {  // two real pixel lines per complex transform
+      c.nreal = ny * nx;
+      c.nlines = (ny * nx + 1) / 2;
+    }
     HIP_TRY(ctx, timed_on(ctx, s, NLOS_PASS_RSD_PHASOR, [&] {
       return p->gen_t ? nlos::launch_gen_contig(p->gt, false, nlos::CL_REAL, nlos::CS_BINS, c, s)
-                      : nlos::launch_contig((int)nt, false, nlos::CL_REAL, nlos::CS_BINS, c, tw, s, sp);
+                      : nlos::launch_contig((int)nt, false, nlos::CL_REAL_PAIR, nlos::CS_BINS, c, tw, s, sp);
     }));
   }
   // 2. x-FFT of the top-left padded planes: lines along x, columns f

@@ -15,7 +15,9 @@ enum { SP_F32 = 0, SP_F16 = 1, SP_BF16 = 2 };
 enum { LD_C64 = 0, LD_TAU_SCALED = 1 };
 enum { ST_C64 = 0, ST_ABS2_IMG = 1, ST_ABS_IMG = 2, ST_C64_SCALED = 3 };
 // contig_fft load / store modes
-enum { CL_C64 = 0, CL_REAL = 1 };
+// CL_REAL_PAIR: line ln is two real lines, 2 ln (real part) and 2 ln + 1 (imaginary part,
+// zero beyond nreal), split again by the CS_BINS store
+enum { CL_C64 = 0, CL_REAL = 1, CL_REAL_PAIR = 2 };
 enum { CS_C64 = 0, CS_ABS_IMG = 1, CS_BINS = 2, CS_ABS2_MAX = 3 };
 
 // Lines along a strided axis.  Element n of line `col` in plane `plane` is at
@@ -53,6 +55,7 @@ struct ContigArgs {
   int nbins;
   const int* e_in;     // FP16 input: holds value * 2^(*e_in)
   const int* e_out;    // CS_BINS with FP16 output: written as value * 2^(*e_out)
+  long long nreal;     // CL_REAL_PAIR: number of real input lines (nlines = ceil(nreal / 2))
 };
 
 // f-k pass 1: tau[ny][nx][nt] (float) -> half spectrum out[ny][Mx/2 + 1][nt] with
