@@ -76,11 +76,12 @@ def test_bin_hot_bin_aggregation(ctx):
 
 
 # (nx, ny, nt, bin_ps, n events, invalid fraction, t0): the tile layouts of the tiled path
-# (tp = 8192 // nt pixels per tile) and the per-event path beyond it
+# (tp = 4096 // nt pixels per tile, at most 8192 tiles) and the per-event path beyond it
 LAYOUTS = [
-    (128, 128, 1024, 3, 3_000_000, 0.05, 0),        # 2048 tiles of 8 pixels
-    (256, 256, 512, 7, 1_000_000, 0.02, 0),         # 4096 tiles of 16 pixels, sparse runs
-    (91, 90, 8192, 1, 400_000, 0.01, 0),            # 8190 tiles of one pixel
+    (128, 128, 1024, 3, 3_000_000, 0.05, 0),        # 4096 tiles of 4 pixels
+    (256, 256, 512, 7, 1_000_000, 0.02, 0),         # 8192 tiles of 8 pixels (the most), sparse runs
+    (91, 90, 4096, 1, 400_000, 0.01, 0),            # 8190 tiles of one pixel
+    (91, 90, 8192, 1, 400_000, 0.01, 0),            # nt above the tile size: per-event path
     (40, 30, 700, 4093, 2_000_000, 0.1, 12345),     # ragged last tile, odd bin width, t0
     (32, 32, 256, 5, 16_789_505, 0.01, 0),          # more than 2048 chunks: two gather rounds
     (8, 8, 64, 1, 100_000, 0.0, 0),                 # unit bin width
