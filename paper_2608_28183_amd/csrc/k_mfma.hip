@@ -205,21 +205,35 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
   const unsigned int* inb = static_cast<const unsigned int*>(a.in);
   unsigned int* outb = static_cast<unsigned int*>(a.out);
   const long long ngroups = (a.nwork + 7) / 8;
-  for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    PairItem item[2];
-    bool ok[2];
-    unsigned int raw[2][2][4];
+  // the next group's columns are loaded while this group is transformed
+  PairItem nitem[2];
+  bool nok[2];
+  unsigned int nraw[2][2][4];
+  auto fetch = [&](long long g) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const long long w = g * 8 + 4 * u + wv;
-      ok[u] = w < a.nwork;
-      item[u] = pair_item(ok[u] ? w : 0, a.Mx, a.My);
-      const unsigned int* in = inb + (long long)item[u].ky * a.in_row + (long long)item[u].kx * a.nt + j;
+      nok[u] = w < a.nwork;
+      nitem[u] = pair_item(nok[u] ? w : 0, a.Mx, a.My);
+      const unsigned int* in = inb + (long long)nitem[u].ky * a.in_row + (long long)nitem[u].kx * a.nt + j;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) raw[u][q][r] = ok[u] ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
+        for (int r = 0; r < 4; ++r) nraw[u][q][r] = nok[u] ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
     }
+  };
+  if ((long long)blockIdx.x < ngroups) fetch(blockIdx.x);
+  for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const PairItem item[2] = {nitem[0], nitem[1]};
+    const bool ok[2] = {nok[0], nok[1]};
+    unsigned int raw[2][2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) raw[u][q][r] = nraw[u][q][r];
+    if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       mf_u4 B3[4];
@@ -308,19 +322,33 @@ __global__ __launch_bounds__(256) void zfft_abs2_mfma(ContigArgs a, const mf_u4*
   const unsigned int* inb = static_cast<const unsigned int*>(a.in);
   float* vol = static_cast<float*>(a.out);
   const long long ngroups = (a.nlines + 7) / 8;
+  // the next group's lines are loaded while this group is transformed
+  unsigned int nraw[2][2][4];
+  auto fetch = [&](long long g) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long long ln = g * 8 + 4 * u + wv;
+      const bool ok = ln < a.nlines;
+      const unsigned int* in = inb + (ok ? ln : 0) * a.in_line + j;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) nraw[u][q][r] = ok ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
+    }
+  };
+  if ((long long)blockIdx.x < ngroups) fetch(blockIdx.x);
   for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
     unsigned int raw[2][2][4];
     long long line[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       line[u] = g * 8 + 4 * u + wv;
-      const bool ok = line[u] < a.nlines;
-      const unsigned int* in = inb + (ok ? line[u] : 0) * a.in_line + j;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) raw[u][q][r] = ok ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
+        for (int r = 0; r < 4; ++r) raw[u][q][r] = nraw[u][q][r];
     }
+    if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (line[u] >= a.nlines) continue;  // uniform
