@@ -40,6 +40,28 @@ __device__ __forceinline__ void emit(const float2* v, int p, Store store) {
   });
 }
 
+// One component (C = 0: real parts, 1: imaginary parts) of write_lds / read_lds, through
+// a float buffer: half the LDS of a complex exchange.
+template <int N, int R, int Ns, int E, int C, class Idx>
+__device__ __forceinline__ void write_lds_part(const float2* v, int p, float* lds, Idx idx) {
+  static_for<E / R>([&](auto b_) {
+    static_for<R>([&](auto r_) {
+      constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+      lds[idx(stage_out_index<N, R, Ns, E>(p, b, r))] = C == 0 ? v[b * R + r].x : v[b * R + r].y;
+    });
+  });
+}
+
+template <int N, int R, int E, class Idx>
+__device__ __forceinline__ void read_lds_part(float* out, int p, const float* lds, Idx idx) {
+  static_for<E / R>([&](auto b_) {
+    static_for<R>([&](auto r_) {
+      constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+      out[b * R + r] = lds[idx(stage_in_index<N, R, E>(p, b, r))];
+    });
+  });
+}
+
 // Stage s (1 or 2) of plan S with twiddles from the global table or from registers.
 template <class S, int STAGE, bool INV>
 __device__ __forceinline__ void apply_stage(float2* v, int p, const float2* __restrict__ tw) {
@@ -55,11 +77,30 @@ __device__ __forceinline__ void apply_stage(float2* v, int, const TwRegs<S>& tw)
 
 // v holds the stage-0 inputs (element stage_in_index<N, R0, E>(p, b, r) at v[b*R0 + r]).
 // Runs every stage; the last stage's outputs stay in v in the order emit_last visits.
-template <class S, bool INV, class Idx, class TW>
+// SPLIT (two-stage plans): the exchange moves the real parts, then the imaginary parts,
+// through a float buffer of half the size (lds is then a float array in disguise).
+template <class S, bool INV, bool SPLIT = false, class Idx, class TW>
 __device__ __forceinline__ void fft_stages(float2* v, int p, float2* lds, Idx idx, const TW& tw) {
   constexpr int N = S::R0 * S::R1 * S::R2;
   constexpr int E = S::E;
   stage_compute<N, S::R0, 1, E, INV>(v, p, nullptr);
+  if constexpr (SPLIT) {
+    static_assert(S::NSTAGE == 2, "split exchange of two-stage plans");
+    float* f = reinterpret_cast<float*>(lds);
+    float re[E];
+    write_lds_part<N, S::R0, 1, E, 0>(v, p, f, idx);
+    __syncthreads();
+    read_lds_part<N, S::R1, E>(re, p, f, idx);
+    __syncthreads();
+    write_lds_part<N, S::R0, 1, E, 1>(v, p, f, idx);
+    __syncthreads();
+    float im[E];
+    read_lds_part<N, S::R1, E>(im, p, f, idx);
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = make_float2(re[j], im[j]);
+    apply_stage<S, 1, INV>(v, p, tw);
+    return;
+  }
   if constexpr (S::NSTAGE >= 2) {
     write_lds<N, S::R0, 1, E>(v, p, lds, idx);
     __syncthreads();
@@ -89,10 +130,10 @@ __device__ __forceinline__ void emit_last(const float2* v, int p, Store store) {
 
 // All stages, then store(n, value) for every output.  SYNC_BEFORE_STORE puts a
 // barrier between the last LDS read and the stores (for stores into LDS).
-template <class S, bool INV, bool SYNC_BEFORE_STORE, class Idx, class TW, class Store>
+template <class S, bool INV, bool SYNC_BEFORE_STORE, bool SPLIT = false, class Idx, class TW, class Store>
 __device__ __forceinline__ void fft_run(float2* v, int p, float2* lds, Idx idx, const TW& tw,
                                         Store store) {
-  fft_stages<S, INV>(v, p, lds, idx, tw);
+  fft_stages<S, INV, SPLIT>(v, p, lds, idx, tw);
   if constexpr (SYNC_BEFORE_STORE) __syncthreads();
   emit_last<S>(v, p, store);
 }

@@ -127,7 +127,10 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   using S = typename C::S;
   constexpr int E = S::E, P = C::P;
   constexpr bool NEED_LDS = (S::NSTAGE > 1) || (ST == CS_BINS);
-  __shared__ float2 lds[NEED_LDS ? C::LDS_ELEMS : 1];
+  // the |.|^2 pass uses LDS only for the exchange of its two-stage plans: real and
+  // imaginary parts in turn, half the LDS, more lines resident per CU
+  constexpr bool SPLIT = ST == CS_ABS2_MAX && S::NSTAGE == 2;
+  __shared__ float2 lds[NEED_LDS ? (SPLIT ? (C::LDS_ELEMS + 1) / 2 : C::LDS_ELEMS) : 1];
   const int tid = threadIdx.x;
   const int l = tid / P;
   const int p = tid % P;
@@ -180,7 +183,9 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
     }
   }
 
-  float2* my = lds + (NEED_LDS ? l * C::LSTRIDE : 0);
+  // a line's part of LDS: LSTRIDE complex values, or LSTRIDE floats when SPLIT
+  float2* my = SPLIT ? reinterpret_cast<float2*>(reinterpret_cast<float*>(lds) + l * C::LSTRIDE)
+                     : lds + (NEED_LDS ? l * C::LSTRIDE : 0);
   auto idx = [&](int n) { return swz(n); };
   if constexpr (ST == CS_BINS) {
     // natural-order spectrum into LDS, then gather the requested bins (four-byte output
@@ -225,7 +230,7 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
       if (a.out != nullptr) static_cast<float*>(a.out)[line * a.out_line + n] = e;
       m = fmaxf(m, e);
     };
-    fft_run<S, INV, false>(v, p, my, idx, tw, store);
+    fft_run<S, INV, false, SPLIT>(v, p, my, idx, tw, store);
     if (a.img != nullptr) {
       constexpr int W = P < 64 ? P : 64;
 #pragma unroll
