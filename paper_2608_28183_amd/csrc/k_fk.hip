@@ -42,19 +42,14 @@ __global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c(FkXArg
   const float s0 = a.unscaled ? 1.f : float(2 * cc) * a.tscale;
   const float s1 = a.unscaled ? 1.f : float(2 * cc + 1) * a.tscale;
 
+  // all loads first (branch-free: the zero padding is the static upper half, or absent),
+  // the t scaling after, so that the thread's loads are in flight together
   float2 v[S::E];
-  static_for<S::E / S::R0>([&](auto b_) {
-    static_for<S::R0>([&](auto r_) {
-      constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-      const int n = stage_in_index<N, S::R0, S::E>(p, b, r);
-      float2 x = make_float2(0.f, 0.f);
-      if (colok && n < a.nx) {
-        const float2 t2 = *reinterpret_cast<const float2*>(a.tau + (y * a.nx + n) * a.nt + 2 * cc);
-        x = make_float2(t2.x * s0, t2.y * s1);
-      }
-      v[b * S::R0 + r] = x;
-    });
-  });
+  const float2* row = reinterpret_cast<const float2*>(a.tau + y * a.nx * a.nt) + (colok ? cc : 0);
+  const long long pitch = a.nt / 2;  // float2 elements between x samples
+  load_first_stage<S>(v, p, a.nx, colok, make_float2(0.f, 0.f), [&](int n) { return row[(long long)n * pitch]; });
+#pragma unroll
+  for (int j = 0; j < S::E; ++j) v[j] = make_float2(v[j].x * s0, v[j].y * s1);
   auto idx = [&](int n) { return n * C::LDS_W + c; };
   fft_run<S, false, true>(v, p, lds, idx, tw, [&](int n, float2 val) { lds[idx(n)] = val; });
   __syncthreads();
