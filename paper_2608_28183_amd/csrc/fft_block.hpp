@@ -75,6 +75,32 @@ __device__ __forceinline__ void apply_stage(float2* v, int, const TwRegs<S>& tw)
   else stage_compute_reg<S::R2, S::E, INV>(v, tw.w2);
 }
 
+// Stage-1 twiddles of a two-stage plan (span R0, radix R1, so Ns R1 = N) from a table in
+// LDS, t[r * R0 + j] = W_N^(j r): short-latency reads in place of global ones.
+template <class S>
+struct TwLds {
+  const float2* t;
+};
+template <class S, int STAGE, bool INV>
+__device__ __forceinline__ void apply_stage(float2* v, int p, const TwLds<S>& tw) {
+  static_assert(STAGE == 1 && S::NSTAGE == 2, "the table holds the stage-1 twiddles of two-stage plans");
+  constexpr int R = S::R1, R0 = S::R0, E = S::E, P = S::P;
+  static_for<E / R>([&](auto b_) {
+    constexpr int b = decltype(b_)::value;
+    const int jm = (p + b * P) % R0;
+    static_for<R - 1>([&](auto r_) {
+      constexpr int r = decltype(r_)::value + 1;
+      float2 w = tw.t[r * R0 + jm];
+      if (INV) w.y = -w.y;
+      v[b * R + r] = cmul(v[b * R + r], w);
+      // eight table reads in flight at a time, not all R - 1 (their registers on top of
+      // the line's would cost occupancy)
+      if constexpr (r % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    });
+    dft<R, INV>(v + b * R);
+  });
+}
+
 // v holds the stage-0 inputs (element stage_in_index<N, R0, E>(p, b, r) at v[b*R0 + r]).
 // Runs every stage; the last stage's outputs stay in v in the order emit_last visits.
 // SPLIT (two-stage plans): the exchange moves the real parts, then the imaginary parts,

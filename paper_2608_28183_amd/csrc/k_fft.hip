@@ -6,6 +6,8 @@
 //                   one plane, so every global access is a T-wide contiguous run;
 //   contig_fft   -- lines along the contiguous axis; a block owns L whole lines.
 // The f-k specific passes (real-input x pass, paired column pass) are in k_fk.hip.
+#include <atomic>
+
 #include "fft_block.hpp"
 #include "nlos_internal.hpp"
 #include "prec.hpp"
@@ -137,7 +139,7 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   const long long line = (long long)blockIdx.x * C::L + l;
   const bool lineok = line < a.nlines;
   float2 v[E];
-  if constexpr (SP == SP_F32 || LD == CL_REAL || LD == CL_REAL_PAIR) {
+  if constexpr (LD == CL_REAL || LD == CL_REAL_PAIR) {
     const bool oddok = LD == CL_REAL_PAIR && 2 * line + 1 < a.nreal;  // the pair's second line
     static_for<E / S::R0>([&](auto b_) {
       static_for<S::R0>([&](auto r_) {
@@ -160,7 +162,8 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
       });
     });
   } else {
-    // four-byte storage: raw loads first, conversion after
+    // complex lines: raw loads first, branch-free (a line past the end reads line 0 and
+    // is zeroed), conversion of four-byte storage after
     using ST_ = Stor<SP>;
     typename ST_::R raw[E];
     const typename ST_::T* in = static_cast<const typename ST_::T*>(a.in) + (lineok ? line : 0) * a.in_line;
@@ -223,11 +226,14 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
     }
   } else if constexpr (ST == CS_ABS2_MAX) {
     // |v|^2 * oscale into out[line][n < n_out] and the max over the line into img[line]
+    // (a line past the end holds zeros: it adds nothing to m and stores nothing)
     float m = 0.f;
+    float* orow = a.out != nullptr ? static_cast<float*>(a.out) + (lineok ? line : 0) * a.out_line : nullptr;
+    const bool wr = lineok && orow != nullptr;
     auto store = [&](int n, float2 val) {
-      if (!lineok || n >= (HALF ? N / 2 : a.n_out)) return;
+      if (n >= (HALF ? N / 2 : a.n_out)) return;
       const float e = (val.x * val.x + val.y * val.y) * a.oscale;
-      if (a.out != nullptr) static_cast<float*>(a.out)[line * a.out_line + n] = e;
+      if (wr) orow[n] = e;
       m = fmaxf(m, e);
     };
     fft_run<S, INV, false, SPLIT>(v, p, my, idx, tw, store);
@@ -255,9 +261,102 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   }
 }
 
+// The FP32 z-IFFT of a zero-padded f-k volume (the upper half of every line is zero
+// padding, the lower half of the outputs is kept), |.|^2 * oscale and the max over each
+// line, as contig_fft<N, true, CL_C64, CS_ABS2_MAX, SP_F32, true> computes it, for
+// two-stage plans.  The blocks stay resident and walk groups of L lines (group g, then
+// g + gridDim.x, ...): the next group's samples are loaded while the current group is
+// transformed, and the stage-1 twiddles sit in LDS for the block's lifetime.  A line past
+// the end (in the last group) stands in for the group's first line: it reads that line,
+// so it computes the same values and stores them to the same places, and every thread
+// issues the same stores, which lets the wait for the next group's loads leave this
+// group's stores in flight.  a.out must not be null.
+template <int N>
+__global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void zifft_abs2_stream(
+    ContigArgs a, const float2* __restrict__ tw, long long ngroups) {
+  using C = ContigCfg<N, ContigTune<N>::E>;
+  using S = typename C::S;
+  constexpr int E = S::E, P = C::P, L = C::L, R0 = S::R0, R1 = S::R1;
+  static_assert(S::NSTAGE == 2 && R0 * R1 == N, "two-stage plans");
+  __shared__ float xch[L * C::LSTRIDE];  // the exchange, one component at a time
+  __shared__ float2 wt[R1 * R0];         // wt[r * R0 + j] = W_N^(j r)
+  const int tid = threadIdx.x;
+  const int l = tid / P;
+  const int p = tid % P;
+  for (int k = tid; k < R1 * R0; k += C::THREADS) wt[k] = tw[(k % R0) * (k / R0) * (kTwiddleN / N)];
+
+  const float2* in = static_cast<const float2*>(a.in);
+  float2 raw[E / 2];  // elements p + r P (r < E/2) of the line: its nonzero half
+  auto fetch = [&](long long g) {
+    const long long line = g * L + l;
+    const float2* row = in + (line < a.nlines ? line : g * L) * a.in_line;
+    static_for<E / 2>([&](auto r_) { raw[decltype(r_)::value] = row[p + decltype(r_)::value * P]; });
+  };
+  float2* my = reinterpret_cast<float2*>(xch + l * C::LSTRIDE);
+  auto idx = [&](int n) { return swz(n); };
+  long long g = blockIdx.x;
+  if (g < ngroups) fetch(g);
+  for (; g < ngroups; g += gridDim.x) {
+    float2 v[E];
+#pragma unroll
+    for (int j = 0; j < E / 2; ++j) v[j] = raw[j];
+#pragma unroll
+    for (int j = E / 2; j < E; ++j) v[j] = make_float2(0.f, 0.f);
+    const long long line0 = g * L + l;
+    const long long line = line0 < a.nlines ? line0 : g * L;
+    if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+
+    float m = 0.f;
+    float* orow = static_cast<float*>(a.out) + line * a.out_line;
+    auto store = [&](int n, float2 val) {
+      if (n >= N / 2) return;
+      const float e = (val.x * val.x + val.y * val.y) * a.oscale;
+      orow[n] = e;
+      m = fmaxf(m, e);
+    };
+    fft_run<S, true, false, true>(v, p, my, idx, TwLds<S>{wt}, store);
+    if (a.img != nullptr) {
+      constexpr int W = P < 64 ? P : 64;
+#pragma unroll
+      for (int off = 1; off < W; off <<= 1) m = fmaxf(m, __shfl_xor(m, off, W));
+      if ((p % W) == 0) atomicMax(reinterpret_cast<unsigned int*>(a.img) + line, __float_as_uint(m));
+    }
+    __syncthreads();  // every read of this group's exchange before the next group's writes
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+// Blocks of `kernel` (of `threads` threads) resident on the whole current device, CUs
+// times blocks per CU, cached per device; 0 if the runtime cannot tell.
+template <class K>
+static long long resident_blocks(K kernel, int threads) {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < 64) {
+    const int v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+  }
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || cus <= 0 || per <= 0)
+    return 0;
+  if (dev < 64) cache[dev].store(cus * per, std::memory_order_relaxed);
+  return (long long)cus * per;
+}
+
+template <int N>
+static hipError_t launch_zifft_stream(const ContigArgs& a, const float2* tw, hipStream_t s) {
+  using C = ContigCfg<N, ContigTune<N>::E>;
+  const long long ngroups = (a.nlines + C::L - 1) / C::L;
+  const long long res = resident_blocks(zifft_abs2_stream<N>, C::THREADS);
+  const long long nb = res > 0 && res < ngroups ? res : ngroups;
+  hipLaunchKernelGGL((zifft_abs2_stream<N>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw, ngroups);
+  return hipGetLastError();
+}
 
 // (samples per thread, columns per block) of the strided passes, from timing sweeps at
 // 512-point lines (256x256x512 f-k): forward y pass E=16 T=16, inverse passes E=8 T=16;
@@ -366,6 +465,8 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
   if (half) {
     if (sp == SP_F16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16, true>(n, a, tw, s);
     if (sp == SP_BF16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16, true>(n, a, tw, s);
+    if (sp == SP_F32 && n == 1024 && a.out != nullptr) return launch_zifft_stream<1024>(a, tw, s);
+    if (sp == SP_F32 && n == 512 && a.out != nullptr) return launch_zifft_stream<512>(a, tw, s);
     if (sp == SP_F32) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F32, true>(n, a, tw, s);
   }
   if (sp == SP_F16 && inverse && ld == CL_C64 && st == CS_ABS2_MAX)

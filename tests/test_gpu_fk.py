@@ -32,7 +32,10 @@ def test_fk_c1(ctx):
 # (ny, nx, nt, pad): tiny, non-square, unpadded, the longest lines on each axis
 SHAPES = [(4, 4, 4, 2), (8, 8, 8, 1), (16, 8, 32, 2), (8, 32, 16, 1), (32, 16, 64, 2),
           (4, 1024, 8, 2), (1024, 4, 8, 2), (4, 4, 1024, 2), (8, 8, 2048, 1), (64, 64, 128, 2),
-          (8, 2048, 8, 1), (128, 8, 16, 2)]
+          (8, 2048, 8, 1), (128, 8, 16, 2),
+          # padded 512- and 1024-point z lines: a ragged last line group, and more groups
+          # than the device holds blocks at once (blocks walk several groups)
+          (5, 7, 256, 2), (9, 13, 512, 2), (99, 70, 512, 2), (132, 126, 256, 2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
