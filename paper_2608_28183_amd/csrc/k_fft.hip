@@ -108,6 +108,82 @@ __global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_fft(S
   fft_run<S, INV, false>(v, p, lds, idx, tw, store);
 }
 
+// FP32 complex lines along a strided axis with non-temporal loads and stores (the f-k y,
+// inverse x and inverse y passes), as strided_fft<N, E, T, INV, LD_C64, ST_C64, SP_F32,
+// true> computes them when n_in is N or N/2 (IN_HALF: the upper half is zero padding) and
+// n_out is N or N/2 (OUT_HALF: the lower half is kept).  The blocks stay resident and
+// walk (plane, column tile) items, item i then i + gridDim.x, ...: the next item's
+// samples are loaded while the current item is transformed, and the stage twiddles stay
+// in registers for the block's lifetime.  A column past ncols (in the last tile) stands
+// in for the tile's first column: it reads that column, computes the same values and
+// stores them to the same places, so every thread issues the same stores and the wait
+// for the prefetched loads leaves the item's stores in flight.
+template <int N, int E, int T_, bool INV, bool IN_HALF, bool OUT_HALF>
+__global__ __launch_bounds__((StridedCfg<N, E, T_>::THREADS)) void strided_c64_stream(
+    StridedArgs a, const float2* __restrict__ tw, int ntiles, int nitems) {
+  using C = StridedCfg<N, E, T_>;
+  using S = typename C::S;
+  constexpr int T = C::T, E_ = S::E, P = S::P;
+  constexpr int RL = S::NSTAGE == 1 ? S::R0 : (S::NSTAGE == 2 ? S::R1 : S::R2);  // last radix
+  constexpr int NR = IN_HALF ? E_ / 2 : E_;  // nonzero inputs per thread
+  static_assert(S::R0 == E_ && RL % 2 == 0, "first radix E, even last radix");
+  __shared__ float2 lds[C::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int c = tid % T;
+  const int p = tid / T;
+  TwRegs<S> twr;
+  twr.load(p, tw);
+  // the twiddles arrive before the first item's loads are issued: the waits of the loop
+  // then count only that loop's own loads and stores
+  __builtin_amdgcn_s_waitcnt(0);
+
+  // the thread's column and plane offset of item it (a column past the end: the tile's first)
+  auto column = [&](int it, int& plane) {
+    plane = (unsigned)it / (unsigned)ntiles;
+    const int col0 = (it - plane * ntiles) * T;
+    return col0 + c < a.ncols ? col0 + c : col0;
+  };
+  float2 raw[NR];  // elements p + r P, r < NR, of the column
+  auto fetch = [&](int it) {
+    int plane;
+    const int col = column(it, plane);
+    const float2* in = static_cast<const float2*>(a.in) + plane * a.in_plane + col + (long long)p * a.in_line;
+    static_for<NR>([&](auto r_) {
+      constexpr int r = decltype(r_)::value;
+      raw[r] = ld_stream(in + (long long)(r * P) * a.in_line);
+    });
+  };
+  auto idx = [&](int n) { return n * C::LDS_W + c; };
+  int it = blockIdx.x;
+  if (it < nitems) fetch(it);
+  // the first item's samples are needed at once; waiting here also leaves the loop's
+  // own waits free of the loads issued before it
+  __builtin_amdgcn_s_waitcnt(0);
+  for (; it < nitems; it += gridDim.x) {
+    float2 v[E_];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = raw[j];
+#pragma unroll
+    for (int j = NR; j < E_; ++j) v[j] = make_float2(0.f, 0.f);
+    int plane;
+    const int col = column(it, plane);
+    if (it + (int)gridDim.x < nitems) fetch(it + gridDim.x);
+
+    fft_stages<S, INV>(v, p, lds, idx, twr);
+    // last stage: butterfly b of thread p holds outputs n = p + b P + r (N / RL); the
+    // lower half is r < RL / 2
+    float2* out = static_cast<float2*>(a.out) + plane * a.out_plane + col;
+    static_for<E_ / RL>([&](auto b_) {
+      static_for<RL>([&](auto r_) {
+        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
+        if constexpr (!OUT_HALF || r < RL / 2)
+          st_stream(out + (long long)(p + b * P + r * (N / RL)) * a.out_line, v[b * RL + r]);
+      });
+    });
+    __syncthreads();  // every read of this item's exchanges before the next item's writes
+  }
+}
+
 // ---------------------------------------------------------------------------
 // contiguous lines
 // ---------------------------------------------------------------------------
@@ -398,8 +474,44 @@ static hipError_t launch_strided_inv(int n, const StridedArgs& a, int nplanes, c
   }
 }
 
+template <int N, bool INV, bool IN_HALF, bool OUT_HALF>
+static hipError_t launch_strided_stream_n(const StridedArgs& a, int nplanes, const float2* tw, hipStream_t s) {
+  using Tn = StridedTune<N, INV, LD_C64, ST_C64, SP_F32>;
+  using C = StridedCfg<N, Tn::E, Tn::T>;
+  const int ntiles = (a.ncols + C::T - 1) / C::T;
+  const int nitems = ntiles * nplanes;
+  auto k = strided_c64_stream<N, Tn::E, Tn::T, INV, IN_HALF, OUT_HALF>;
+  const long long res = resident_blocks(k, C::THREADS);
+  const long long nb = res > 0 && res < nitems ? res : nitems;
+  hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw, ntiles, nitems);
+  return hipGetLastError();
+}
+
+// The streaming form of the FP32 f-k strided passes: forward with a zero-padded upper
+// half, inverse with the lower half of the outputs kept.  Returns false (nothing
+// launched) for other shapes, which strided_fft takes.
+static bool launch_strided_stream(int n, bool inverse, const StridedArgs& a, int nplanes, const float2* tw,
+                                  hipStream_t s, hipError_t& err) {
+  if (a.ncols <= 0 || nplanes <= 0 || (long long)a.ncols * nplanes > (1LL << 30)) return false;
+  const bool fwd_half = !inverse && 2 * a.n_in == n && a.n_out == n;
+  const bool inv_half = inverse && a.n_in == n && 2 * a.n_out == n;
+  if (!fwd_half && !inv_half) return false;
+  switch (n) {
+    case 256: err = inverse ? launch_strided_stream_n<256, true, false, true>(a, nplanes, tw, s)
+                            : launch_strided_stream_n<256, false, true, false>(a, nplanes, tw, s); return true;
+    case 512: err = inverse ? launch_strided_stream_n<512, true, false, true>(a, nplanes, tw, s)
+                            : launch_strided_stream_n<512, false, true, false>(a, nplanes, tw, s); return true;
+    case 1024: err = inverse ? launch_strided_stream_n<1024, true, false, true>(a, nplanes, tw, s)
+                             : launch_strided_stream_n<1024, false, true, false>(a, nplanes, tw, s); return true;
+    default: return false;
+  }
+}
+
 hipError_t launch_strided(int n, bool inverse, int ld, int st, const StridedArgs& a, int nplanes,
                           const float2* tw, hipStream_t s, int sp, bool stream) {
+  hipError_t err = hipSuccess;
+  if (stream && sp == SP_F32 && ld == LD_C64 && st == ST_C64 && launch_strided_stream(n, inverse, a, nplanes, tw, s, err))
+    return err;
   if (stream && sp == SP_F32 && ld == LD_C64 && st == ST_C64)
     return inverse ? launch_strided_inv<true, LD_C64, ST_C64, SP_F32, true>(n, a, nplanes, tw, s)
                    : launch_strided_inv<false, LD_C64, ST_C64, SP_F32, true>(n, a, nplanes, tw, s);
