@@ -205,27 +205,31 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
   const unsigned int* inb = static_cast<const unsigned int*>(a.in);
   unsigned int* outb = static_cast<unsigned int*>(a.out);
   const long long ngroups = (a.nwork + 7) / 8;
-  // the next group's columns are loaded while this group is transformed
+  // The next group's columns are loaded while this group is transformed.  An item past
+  // the end (in the last group) stands in for the group's first item: it reads that
+  // column, computes the same values and stores them to the same places, so that every
+  // wave issues the same loads and stores and the wait for the next group's loads leaves
+  // this group's stores in flight.
   PairItem nitem[2];
-  bool nok[2];
   unsigned int nraw[2][2][4];
   auto fetch = [&](long long g) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const long long w = g * 8 + 4 * u + wv;
-      nok[u] = w < a.nwork;
-      nitem[u] = pair_item(nok[u] ? w : 0, a.Mx, a.My);
+      nitem[u] = pair_item(w < a.nwork ? w : g * 8, a.Mx, a.My);
       const unsigned int* in = inb + (long long)nitem[u].ky * a.in_row + (long long)nitem[u].kx * a.nt + j;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) nraw[u][q][r] = nok[u] ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
+        for (int r = 0; r < 4; ++r) nraw[u][q][r] = ld_u32_nt(in + 32 * (8 * q + 4 * hl + r));
     }
   };
   if ((long long)blockIdx.x < ngroups) fetch(blockIdx.x);
+  // the tables and the first group arrive before the loop, whose one wait per group then
+  // counts only the loop's own loads and stores
+  __builtin_amdgcn_s_waitcnt(0);
   for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const PairItem item[2] = {nitem[0], nitem[1]};
-    const bool ok[2] = {nok[0], nok[1]};
     unsigned int raw[2][2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -268,9 +272,10 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
       int kzmax = rem < 0.0 ? -1 : (int)sqrt(rem);
       if (kzmax >= 0 && double(kzmax) * kzmax > rem) --kzmax;
       if (double(kzmax + 1) * (kzmax + 1) <= rem) ++kzmax;
+      // a column without a mirror (its own mirror) stores its own remap twice
+      const bool mir = it.has_mirror;
       unsigned int* o1 = outb + (long long)it.ky * a.out_row + (long long)it.kx * a.nt + lane;
-      unsigned int* o2 = outb + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt + lane;
-      const bool ok1 = ok[u], ok2 = ok[u] && it.has_mirror;
+      unsigned int* o2 = mir ? outb + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt + lane : o1;
 #pragma unroll
       for (int i = 0; i < HALF / 64; ++i) {
         const float kz = (float)(lane + 64 * i);
@@ -290,8 +295,9 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
         const float2 m1 = my[N - 1 - i0], m0 = my[N - i0];
         const float ar = fmaf(fr, s1.x - s0.x, s0.x) * jac, ai = fmaf(fr, s1.y - s0.y, s0.y) * jac;
         const float br = fmaf(fr, m1.x - m0.x, m0.x) * jac, bi = -fmaf(fr, m1.y - m0.y, m0.y) * jac;
-        if (ok1) st_u32_nt(o1 + 64 * i, M::pack(ar, ai));
-        if (ok2) st_u32_nt(o2 + 64 * i, M::pack(br, bi));
+        const unsigned int pa = M::pack(ar, ai);
+        st_u32_nt(o1 + 64 * i, pa);
+        st_u32_nt(o2 + 64 * i, mir ? M::pack(br, bi) : pa);
       }
     }
   }
@@ -301,8 +307,10 @@ __global__ __launch_bounds__(256) void fk_column_pair_mfma(FkPairArgs a, const m
 // z-IFFT of 1024-point columns (512 stored samples, 512 outputs kept), |.|^2, max
 // ---------------------------------------------------------------------------
 
-template <int SP>
-__global__ __launch_bounds__(256) void zfft_abs2_mfma(ContigArgs a, const mf_u4* __restrict__ tb1,
+// VOL: the volume is written (a.out not null).  A line past the end (in the last group)
+// stands in for the group's first line, as in fk_column_pair_mfma.
+template <int SP, bool VOL>
+__global__ __launch_bounds__(256, 3) void zfft_abs2_mfma(ContigArgs a, const mf_u4* __restrict__ tb1,
                                                       const mf_u4* __restrict__ ta3,
                                                       const float2* __restrict__ twt) {
   using M = Mfma<SP>;
@@ -328,21 +336,21 @@ __global__ __launch_bounds__(256) void zfft_abs2_mfma(ContigArgs a, const mf_u4*
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const long long ln = g * 8 + 4 * u + wv;
-      const bool ok = ln < a.nlines;
-      const unsigned int* in = inb + (ok ? ln : 0) * a.in_line + j;
+      const unsigned int* in = inb + (ln < a.nlines ? ln : g * 8) * a.in_line + j;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) nraw[u][q][r] = ok ? ld_u32_nt(in + 32 * (8 * q + 4 * hl + r)) : 0u;
+        for (int r = 0; r < 4; ++r) nraw[u][q][r] = ld_u32_nt(in + 32 * (8 * q + 4 * hl + r));
     }
   };
   if ((long long)blockIdx.x < ngroups) fetch(blockIdx.x);
+  __builtin_amdgcn_s_waitcnt(0);  // tables and the first group before the loop
   for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
     unsigned int raw[2][2][4];
     long long line[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      line[u] = g * 8 + 4 * u + wv;
+      line[u] = g * 8 + 4 * u + wv < a.nlines ? g * 8 + 4 * u + wv : g * 8;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -351,20 +359,19 @@ __global__ __launch_bounds__(256) void zfft_abs2_mfma(ContigArgs a, const mf_u4*
     if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      if (line[u] >= a.nlines) continue;  // uniform
       mf_u4 B3[4];
       col1024_first<SP>(B1, tl, lane, raw[u], B3);
       mf_acc d = {};
 #pragma unroll
       for (int q = 0; q < 4; ++q) d = M::mma(A3[q], B3[q], d);
       float mx = 0.f;
-      float* vrow = vol != nullptr ? vol + line[u] * a.out_line + j : nullptr;
+      float* vrow = VOL ? vol + line[u] * a.out_line + j : nullptr;
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const float re = d[jj] * sc, im = d[jj + 8] * sc;
         const float v = (re * re + im * im) * a.oscale;
         mx = fmaxf(mx, v);
-        if (vrow != nullptr) vrow[32 * mf_out_index(jj, hl)] = v;
+        if constexpr (VOL) vrow[32 * mf_out_index(jj, hl)] = v;
       }
       if (a.img != nullptr) {
 #pragma unroll
@@ -433,10 +440,9 @@ hipError_t launch_zfft_abs2_mfma(const ContigArgs& a, const MfmaTables& t, const
   const mf_u4* ta3 = static_cast<const mf_u4*>(t.a32[1][0][bf]);   // inverse, unscaled, block 0
   const long long blocks = (a.nlines + 7) / 8;
   const unsigned grid = (unsigned)(blocks < 2048 ? blocks : 2048);
-  if (sp == SP_F16)
-    hipLaunchKernelGGL(zfft_abs2_mfma<SP_F16>, dim3(grid), dim3(256), 0, s, a, tb1, ta3, tw);
-  else
-    hipLaunchKernelGGL(zfft_abs2_mfma<SP_BF16>, dim3(grid), dim3(256), 0, s, a, tb1, ta3, tw);
+  auto k = sp == SP_F16 ? (a.out ? zfft_abs2_mfma<SP_F16, true> : zfft_abs2_mfma<SP_F16, false>)
+                        : (a.out ? zfft_abs2_mfma<SP_BF16, true> : zfft_abs2_mfma<SP_BF16, false>);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, a, tb1, ta3, tw);
   return hipGetLastError();
 }
 
