@@ -6,8 +6,6 @@
 //                   one plane, so every global access is a T-wide contiguous run;
 //   contig_fft   -- lines along the contiguous axis; a block owns L whole lines.
 // The f-k specific passes (real-input x pass, paired column pass) are in k_fk.hip.
-#include <atomic>
-
 #include "fft_block.hpp"
 #include "nlos_internal.hpp"
 #include "prec.hpp"
@@ -405,30 +403,12 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void zif
 // launchers
 // ---------------------------------------------------------------------------
 
-// Blocks of `kernel` (of `threads` threads) resident on the whole current device, CUs
-// times blocks per CU, cached per device; 0 if the runtime cannot tell.
-template <class K>
-static long long resident_blocks(K kernel, int threads) {
-  static std::atomic<int> cache[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-  if (dev < 64) {
-    const int v = cache[dev].load(std::memory_order_relaxed);
-    if (v > 0) return v;
-  }
-  int cus = 0, per = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || cus <= 0 || per <= 0)
-    return 0;
-  if (dev < 64) cache[dev].store(cus * per, std::memory_order_relaxed);
-  return (long long)cus * per;
-}
 
 template <int N>
 static hipError_t launch_zifft_stream(const ContigArgs& a, const float2* tw, hipStream_t s) {
   using C = ContigCfg<N, ContigTune<N>::E>;
   const long long ngroups = (a.nlines + C::L - 1) / C::L;
-  const long long res = resident_blocks(zifft_abs2_stream<N>, C::THREADS);
+  const long long res = resident_blocks<zifft_abs2_stream<N>>(C::THREADS);
   const long long nb = res > 0 && res < ngroups ? res : ngroups;
   hipLaunchKernelGGL((zifft_abs2_stream<N>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw, ngroups);
   return hipGetLastError();
@@ -481,15 +461,16 @@ static hipError_t launch_strided_stream_n(const StridedArgs& a, int nplanes, con
   const int ntiles = (a.ncols + C::T - 1) / C::T;
   const int nitems = ntiles * nplanes;
   auto k = strided_c64_stream<N, Tn::E, Tn::T, INV, IN_HALF, OUT_HALF>;
-  const long long res = resident_blocks(k, C::THREADS);
+  const long long res = resident_blocks<strided_c64_stream<N, Tn::E, Tn::T, INV, IN_HALF, OUT_HALF>>(C::THREADS);
   const long long nb = res > 0 && res < nitems ? res : nitems;
   hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw, ntiles, nitems);
   return hipGetLastError();
 }
 
 // The streaming form of the FP32 f-k strided passes: forward with a zero-padded upper
-// half, inverse with the lower half of the outputs kept.  Returns false (nothing
-// launched) for other shapes, which strided_fft takes.
+// half, inverse with the lower half of the outputs kept, 256- and 512-point lines (1024
+// would need 250 VGPRs).  Returns false (nothing launched) for other shapes, which
+// strided_fft takes.
 static bool launch_strided_stream(int n, bool inverse, const StridedArgs& a, int nplanes, const float2* tw,
                                   hipStream_t s, hipError_t& err) {
   if (a.ncols <= 0 || nplanes <= 0 || (long long)a.ncols * nplanes > (1LL << 30)) return false;
@@ -501,8 +482,6 @@ static bool launch_strided_stream(int n, bool inverse, const StridedArgs& a, int
                             : launch_strided_stream_n<256, false, true, false>(a, nplanes, tw, s); return true;
     case 512: err = inverse ? launch_strided_stream_n<512, true, false, true>(a, nplanes, tw, s)
                             : launch_strided_stream_n<512, false, true, false>(a, nplanes, tw, s); return true;
-    case 1024: err = inverse ? launch_strided_stream_n<1024, true, false, true>(a, nplanes, tw, s)
-                             : launch_strided_stream_n<1024, false, true, false>(a, nplanes, tw, s); return true;
     default: return false;
   }
 }

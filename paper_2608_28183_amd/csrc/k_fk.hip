@@ -437,6 +437,76 @@ hipError_t launch_fk_scales(const float* tau, long long n, int nt, float* partia
 // launchers
 // ---------------------------------------------------------------------------
 
+// The FP32 x pass as resident blocks that walk (y, tile of T column pairs) items, item i
+// then i + gridDim.x, ...: the next item's samples load while the current item is
+// transformed, the stage twiddles stay in registers.  IN_HALF: nx = N/2 (the upper half
+// is the zero padding), else nx = N.  A column pair past nt/2 (in the last tile) stands in
+// for the tile's first pair: it reads it, computes the same values and stores them to the
+// same place, so every thread issues the same stores (the wait for the next item's loads
+// then leaves the item's stores in flight).  Same results as fk_xr2c<N, E, T, SP_F32>.
+template <int N, int E, int T, bool IN_HALF>
+__global__ __launch_bounds__((StridedCfg<N, E, T>::THREADS)) void fk_xr2c_stream(FkXArgs a,
+                                                                                 const float2* __restrict__ tw,
+                                                                                 int ntiles, int nitems) {
+  using C = StridedCfg<N, E, T>;
+  using S = typename C::S;
+  constexpr int P = S::P, E_ = S::E, NR = IN_HALF ? E_ / 2 : E_;
+  static_assert(S::R0 == E_, "first radix E");
+  __shared__ float2 lds[N * C::LDS_W];
+  const int tid = threadIdx.x;
+  const int c = tid % T;
+  const int p = tid / T;
+  TwRegs<S> twr;
+  twr.load(p, tw);
+  const int ncc = a.nt / 2;            // complex lines (real t-column pairs) per y
+  const long long pitch = a.nt / 2;    // float2 elements between x samples
+  auto pair = [&](int it, int& y) {
+    y = (unsigned)it / (unsigned)ntiles;
+    const int cc0 = (it - y * ntiles) * T;
+    return cc0 + c < ncc ? cc0 + c : cc0;
+  };
+  float2 raw[NR];  // x samples p + r P, r < NR
+  auto fetch = [&](int it) {
+    int y;
+    const int cc = pair(it, y);
+    const float2* row = reinterpret_cast<const float2*>(a.tau + (long long)y * a.nx * a.nt) + cc;
+    static_for<NR>([&](auto r_) {
+      constexpr int r = decltype(r_)::value;
+      raw[r] = row[(long long)(p + r * P) * pitch];
+    });
+  };
+  auto idx = [&](int n) { return n * C::LDS_W + c; };
+  int it = blockIdx.x;
+  if (it < nitems) fetch(it);
+  __builtin_amdgcn_s_waitcnt(0);  // twiddles and the first item before the loop
+  for (; it < nitems; it += gridDim.x) {
+    int y;
+    const int cc = pair(it, y);
+    const float s0 = a.unscaled ? 1.f : float(2 * cc) * a.tscale;
+    const float s1 = a.unscaled ? 1.f : float(2 * cc + 1) * a.tscale;
+    float2 v[E_];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = make_float2(raw[j].x * s0, raw[j].y * s1);
+#pragma unroll
+    for (int j = NR; j < E_; ++j) v[j] = make_float2(0.f, 0.f);
+    if (it + (int)gridDim.x < nitems) fetch(it + gridDim.x);
+    fft_run<S, false, true>(v, p, lds, idx, twr, [&](int n, float2 val) { lds[idx(n)] = val; });
+    __syncthreads();
+    float4* out = reinterpret_cast<float4*>(static_cast<float2*>(a.out) + (long long)y * a.out_plane + 2 * cc);
+    // A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / (2i), k <= N/2: k = p + r P for
+    // r < E/2, and k = N/2 on p = 0
+    auto put = [&](int k) {
+      const float2 zk = lds[idx(k)];
+      const float2 zm = lds[idx((N - k) & (N - 1))];
+      st_stream(out + (long long)k * (a.nt / 2), make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y),
+                                                            0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)));
+    };
+    static_for<E_ / 2>([&](auto r_) { put(p + decltype(r_)::value * P); });
+    if (p == 0) put(N / 2);
+    __syncthreads();  // this item's LDS reads before the next item's writes
+  }
+}
+
 // samples per thread and real-column pairs per block of the x pass (timing sweep at
 // 512-point lines: E=8, T=16)
 template <int N>
@@ -449,6 +519,20 @@ template <int N, int SP>
 static hipError_t launch_xr2c_n(const FkXArgs& a, int ny, const float2* tw, hipStream_t s) {
   constexpr int E = XTune<N>::E, T = XTune<N>::T;
   using C = StridedCfg<N, E, T>;
+  // (1024-point lines would need 235+ VGPRs in the streaming form: they keep fk_xr2c)
+  if constexpr (SP == SP_F32 && (N == 256 || N == 512)) {
+    const int ntiles = (a.nt / 2 + T - 1) / T;
+    if ((a.nx == N || 2 * a.nx == N) && ntiles > 0 && ny > 0 && (long long)ntiles * ny < (1LL << 30)) {
+      const int nitems = ntiles * ny;
+      const bool half = 2 * a.nx == N;
+      auto k = half ? fk_xr2c_stream<N, E, T, true> : fk_xr2c_stream<N, E, T, false>;
+      const long long res = half ? resident_blocks<fk_xr2c_stream<N, E, T, true>>(C::THREADS)
+                                 : resident_blocks<fk_xr2c_stream<N, E, T, false>>(C::THREADS);
+      const long long nb = res > 0 && res < nitems ? res : nitems;
+      hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw, ntiles, nitems);
+      return hipGetLastError();
+    }
+  }
   dim3 grid((unsigned)((a.nt / 2 + T - 1) / T), (unsigned)ny);
   hipLaunchKernelGGL((fk_xr2c<N, E, T, SP>), grid, dim3(C::THREADS), 0, s, a, tw);
   return hipGetLastError();

@@ -3,10 +3,32 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 
 namespace nlos {
+
+// Blocks of kernel K (launched with `threads` threads) resident on the whole current
+// device at once, CUs times blocks per CU from the occupancy query, cached per kernel and
+// device; 0 if the runtime cannot tell.  Sizes the grids of the kernels whose blocks stay
+// resident and walk work items.
+template <auto K>
+inline long long resident_blocks(int threads) {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < 64) {
+    const int v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+  }
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, threads, 0) != hipSuccess || cus <= 0 || per <= 0)
+    return 0;
+  if (dev < 64) cache[dev].store(cus * per, std::memory_order_relaxed);
+  return (long long)cus * per;
+}
 
 // storage precision of complex intermediates (float2, __half2, __hip_bfloat162)
 enum { SP_F32 = 0, SP_F16 = 1, SP_BF16 = 2 };

@@ -35,7 +35,9 @@ SHAPES = [(4, 4, 4, 2), (8, 8, 8, 1), (16, 8, 32, 2), (8, 32, 16, 1), (32, 16, 6
           (8, 2048, 8, 1), (128, 8, 16, 2),
           # padded 512- and 1024-point z lines: a ragged last line group, and more groups
           # than the device holds blocks at once (blocks walk several groups)
-          (5, 7, 256, 2), (9, 13, 512, 2), (99, 70, 512, 2), (132, 126, 256, 2)]
+          (5, 7, 256, 2), (9, 13, 512, 2), (99, 70, 512, 2), (132, 126, 256, 2),
+          # 256- and 512-point x lines with a ragged last tile of column pairs, padded and not
+          (4, 128, 40, 2), (20, 256, 24, 2), (8, 256, 16, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
