@@ -75,22 +75,27 @@ __device__ __forceinline__ void apply_stage(float2* v, int, const TwRegs<S>& tw)
   else stage_compute_reg<S::R2, S::E, INV>(v, tw.w2);
 }
 
-// Stage-1 twiddles of a two-stage plan (span R0, radix R1, so Ns R1 = N) from a table in
-// LDS, t[r * R0 + j] = W_N^(j r): short-latency reads in place of global ones.
+// Inter-stage twiddles from tables in LDS (short-latency reads in place of global ones).
+// Stage 1 (span R0, radix R1): t[r * R0 + j] = W_{R0 R1}^(j r), r < R1, j < R0.
+// Stage 2 of three-stage plans (span R0 R1, radix R2): t2[(r - 1) R0 R1 + j] = W_N^(j r),
+// 1 <= r < R2, j < R0 R1.
 template <class S>
 struct TwLds {
   const float2* t;
+  const float2* t2;
 };
 template <class S, int STAGE, bool INV>
 __device__ __forceinline__ void apply_stage(float2* v, int p, const TwLds<S>& tw) {
-  static_assert(STAGE == 1 && S::NSTAGE == 2, "the table holds the stage-1 twiddles of two-stage plans");
-  constexpr int R = S::R1, R0 = S::R0, E = S::E, P = S::P;
+  static_assert(S::NSTAGE >= 2 && STAGE <= S::NSTAGE - 1, "a stage after the first");
+  constexpr int R = STAGE == 1 ? S::R1 : S::R2;
+  constexpr int NS = STAGE == 1 ? S::R0 : S::R0 * S::R1;  // span of the stage
+  constexpr int E = S::E, P = S::P;
   static_for<E / R>([&](auto b_) {
     constexpr int b = decltype(b_)::value;
-    const int jm = (p + b * P) % R0;
+    const int jm = (p + b * P) % NS;
     static_for<R - 1>([&](auto r_) {
       constexpr int r = decltype(r_)::value + 1;
-      float2 w = tw.t[r * R0 + jm];
+      float2 w = STAGE == 1 ? tw.t[r * NS + jm] : tw.t2[(r - 1) * NS + jm];
       if (INV) w.y = -w.y;
       v[b * R + r] = cmul(v[b * R + r], w);
       // eight table reads in flight at a time, not all R - 1 (their registers on top of
@@ -103,28 +108,44 @@ __device__ __forceinline__ void apply_stage(float2* v, int p, const TwLds<S>& tw
 
 // v holds the stage-0 inputs (element stage_in_index<N, R0, E>(p, b, r) at v[b*R0 + r]).
 // Runs every stage; the last stage's outputs stay in v in the order emit_last visits.
-// SPLIT (two-stage plans): the exchange moves the real parts, then the imaginary parts,
-// through a float buffer of half the size (lds is then a float array in disguise).
+// SPLIT (two- and three-stage plans): each exchange moves the real parts, then the
+// imaginary parts, through a float buffer of half the size (lds is then a float array in
+// disguise).
 template <class S, bool INV, bool SPLIT = false, class Idx, class TW>
 __device__ __forceinline__ void fft_stages(float2* v, int p, float2* lds, Idx idx, const TW& tw) {
   constexpr int N = S::R0 * S::R1 * S::R2;
   constexpr int E = S::E;
   stage_compute<N, S::R0, 1, E, INV>(v, p, nullptr);
   if constexpr (SPLIT) {
-    static_assert(S::NSTAGE == 2, "split exchange of two-stage plans");
+    static_assert(S::NSTAGE >= 2, "split exchange of multi-stage plans");
     float* f = reinterpret_cast<float*>(lds);
-    float re[E];
-    write_lds_part<N, S::R0, 1, E, 0>(v, p, f, idx);
-    __syncthreads();
-    read_lds_part<N, S::R1, E>(re, p, f, idx);
-    __syncthreads();
-    write_lds_part<N, S::R0, 1, E, 1>(v, p, f, idx);
-    __syncthreads();
-    float im[E];
-    read_lds_part<N, S::R1, E>(im, p, f, idx);
+    {
+      float re[E], im[E];
+      write_lds_part<N, S::R0, 1, E, 0>(v, p, f, idx);
+      __syncthreads();
+      read_lds_part<N, S::R1, E>(re, p, f, idx);
+      __syncthreads();
+      write_lds_part<N, S::R0, 1, E, 1>(v, p, f, idx);
+      __syncthreads();
+      read_lds_part<N, S::R1, E>(im, p, f, idx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = make_float2(re[j], im[j]);
+      for (int j = 0; j < E; ++j) v[j] = make_float2(re[j], im[j]);
+    }
     apply_stage<S, 1, INV>(v, p, tw);
+    if constexpr (S::NSTAGE == 3) {
+      float re[E], im[E];
+      __syncthreads();  // every read of the first exchange before the second's writes
+      write_lds_part<N, S::R1, S::R0, E, 0>(v, p, f, idx);
+      __syncthreads();
+      read_lds_part<N, S::R2, E>(re, p, f, idx);
+      __syncthreads();
+      write_lds_part<N, S::R1, S::R0, E, 1>(v, p, f, idx);
+      __syncthreads();
+      read_lds_part<N, S::R2, E>(im, p, f, idx);
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = make_float2(re[j], im[j]);
+      apply_stage<S, 2, INV>(v, p, tw);
+    }
     return;
   }
   if constexpr (S::NSTAGE >= 2) {

@@ -337,10 +337,10 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
 
 // The FP32 z-IFFT of a zero-padded f-k volume (the upper half of every line is zero
 // padding, the lower half of the outputs is kept), |.|^2 * oscale and the max over each
-// line, as contig_fft<N, true, CL_C64, CS_ABS2_MAX, SP_F32, true> computes it, for
-// two-stage plans.  The blocks stay resident and walk groups of L lines (group g, then
-// g + gridDim.x, ...): the next group's samples are loaded while the current group is
-// transformed, and the stage-1 twiddles sit in LDS for the block's lifetime.  A line past
+// line, as contig_fft<N, true, CL_C64, CS_ABS2_MAX, SP_F32, true> computes it, for two-
+// and three-stage plans.  The blocks stay resident and walk groups of L lines (group g,
+// then g + gridDim.x, ...): the next group's samples are loaded while the current group
+// is transformed, and the inter-stage twiddles sit in LDS for the block's lifetime.  A line past
 // the end (in the last group) stands in for the group's first line: it reads that line,
 // so it computes the same values and stores them to the same places, and every thread
 // issues the same stores, which lets the wait for the next group's loads leave this
@@ -350,14 +350,19 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void zif
     ContigArgs a, const float2* __restrict__ tw, long long ngroups) {
   using C = ContigCfg<N, ContigTune<N>::E>;
   using S = typename C::S;
-  constexpr int E = S::E, P = C::P, L = C::L, R0 = S::R0, R1 = S::R1;
-  static_assert(S::NSTAGE == 2 && R0 * R1 == N, "two-stage plans");
+  constexpr int E = S::E, P = C::P, L = C::L, R0 = S::R0, R1 = S::R1, R2 = S::R2;
+  static_assert(S::NSTAGE == 2 || S::NSTAGE == 3, "two- or three-stage plans");
+  constexpr int NW2 = S::NSTAGE == 3 ? (R2 - 1) * R0 * R1 : 1;
   __shared__ float xch[L * C::LSTRIDE];  // the exchange, one component at a time
-  __shared__ float2 wt[R1 * R0];         // wt[r * R0 + j] = W_N^(j r)
+  __shared__ float2 wt[R1 * R0];         // wt[r * R0 + j] = W_{R0 R1}^(j r)
+  __shared__ float2 wt2[NW2];            // wt2[(r - 1) R0 R1 + j] = W_N^(j r) (three stages)
   const int tid = threadIdx.x;
   const int l = tid / P;
   const int p = tid % P;
-  for (int k = tid; k < R1 * R0; k += C::THREADS) wt[k] = tw[(k % R0) * (k / R0) * (kTwiddleN / N)];
+  for (int k = tid; k < R1 * R0; k += C::THREADS) wt[k] = tw[(k % R0) * (k / R0) * (kTwiddleN / (R0 * R1))];
+  if constexpr (S::NSTAGE == 3)
+    for (int k = tid; k < NW2; k += C::THREADS)
+      wt2[k] = tw[(k % (R0 * R1)) * (1 + k / (R0 * R1)) * (kTwiddleN / N)];
 
   const float2* in = static_cast<const float2*>(a.in);
   float2 raw[E / 2];  // elements p + r P (r < E/2) of the line: its nonzero half
@@ -388,7 +393,7 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void zif
       orow[n] = e;
       m = fmaxf(m, e);
     };
-    fft_run<S, true, false, true>(v, p, my, idx, TwLds<S>{wt}, store);
+    fft_run<S, true, false, true>(v, p, my, idx, TwLds<S>{wt, wt2}, store);
     if (a.img != nullptr) {
       constexpr int W = P < 64 ? P : 64;
 #pragma unroll
@@ -556,6 +561,7 @@ hipError_t launch_contig(int n, bool inverse, int ld, int st, const ContigArgs& 
   if (half) {
     if (sp == SP_F16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F16, true>(n, a, tw, s);
     if (sp == SP_BF16) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_BF16, true>(n, a, tw, s);
+    if (sp == SP_F32 && n == 2048 && a.out != nullptr) return launch_zifft_stream<2048>(a, tw, s);
     if (sp == SP_F32 && n == 1024 && a.out != nullptr) return launch_zifft_stream<1024>(a, tw, s);
     if (sp == SP_F32 && n == 512 && a.out != nullptr) return launch_zifft_stream<512>(a, tw, s);
     if (sp == SP_F32) return launch_contig_inv<true, CL_C64, CS_ABS2_MAX, SP_F32, true>(n, a, tw, s);

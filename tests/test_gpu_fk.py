@@ -37,7 +37,9 @@ SHAPES = [(4, 4, 4, 2), (8, 8, 8, 1), (16, 8, 32, 2), (8, 32, 16, 1), (32, 16, 6
           # than the device holds blocks at once (blocks walk several groups)
           (5, 7, 256, 2), (9, 13, 512, 2), (99, 70, 512, 2), (132, 126, 256, 2),
           # 256- and 512-point x lines with a ragged last tile of column pairs, padded and not
-          (4, 128, 40, 2), (20, 256, 24, 2), (8, 256, 16, 1)]
+          (4, 128, 40, 2), (20, 256, 24, 2), (8, 256, 16, 1),
+          # 2048-point z lines (three-stage plan) with a ragged last line group
+          (5, 5, 1024, 2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
