@@ -236,6 +236,82 @@ __global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair(Fk
   }
 }
 
+// The FP32 column pass of a padded volume (nt = N/2) for three-stage plans, as
+// fk_column_pair<N, E, SP_F32> computes it, with resident blocks that load the next
+// group's columns while they transform the current one; the inter-stage twiddles sit in
+// LDS tables.  An item past the end (in the last group) stands in for the group's first
+// item, and a column without a mirror stores its own remap twice, so every thread issues
+// the same stores and the wait for the next group's loads leaves this group's stores in
+// flight.
+template <int N, int E_>
+__global__ __launch_bounds__((ContigCfg<N, E_>::THREADS)) void fk_column_pair_stream(FkPairArgs a,
+                                                                                    const float2* __restrict__ tw) {
+  using C = ContigCfg<N, E_>;
+  using S = typename C::S;
+  constexpr int E = S::E, P = C::P, L = C::L, HALF = N / 2, R0 = S::R0, R1 = S::R1, R2 = S::R2;
+  static_assert(S::NSTAGE == 3 && R0 == E && HALF % P == 0, "three-stage plans");
+  __shared__ float2 lds[C::LDS_ELEMS];
+  __shared__ float2 wt[R1 * R0];               // W_{R0 R1}^(j r)
+  __shared__ float2 wt2[(R2 - 1) * R0 * R1];   // W_N^(j r), r >= 1
+  const int tid = threadIdx.x;
+  const int l = tid / P;
+  const int p = tid % P;
+  for (int k = tid; k < R1 * R0; k += C::THREADS) wt[k] = tw[(k % R0) * (k / R0) * (kTwiddleN / (R0 * R1))];
+  for (int k = tid; k < (R2 - 1) * R0 * R1; k += C::THREADS)
+    wt2[k] = tw[(k % (R0 * R1)) * (1 + k / (R0 * R1)) * (kTwiddleN / N)];
+  float2* my = lds + l * C::LSTRIDE;
+  auto idx = [&](int n) { return swz(n); };
+  const long long ngroups = (a.nwork + L - 1) / L;
+  const float2* in = static_cast<const float2*>(a.in);
+  float2* outp = static_cast<float2*>(a.out);
+
+  PairItem nit;
+  float2 raw[E / 2];  // samples p + r P (r < E/2) of the column: its stored half
+  auto fetch = [&](long long g) {
+    const long long w = g * L + l;
+    nit = pair_item(w < a.nwork ? w : g * L, a.Mx, a.My);
+    const float2* col = in + (long long)nit.ky * a.in_row + (long long)nit.kx * a.nt;
+    static_for<E / 2>([&](auto r_) {
+      constexpr int r = decltype(r_)::value;
+      raw[r] = ld_stream(col + p + r * P);
+    });
+  };
+  if ((long long)blockIdx.x < ngroups) fetch(blockIdx.x);
+  __builtin_amdgcn_s_waitcnt(0);  // tables and the first group before the loop
+  for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const PairItem it = nit;
+    float2 v[E];
+#pragma unroll
+    for (int j = 0; j < E / 2; ++j) v[j] = raw[j];
+#pragma unroll
+    for (int j = E / 2; j < E; ++j) v[j] = make_float2(0.f, 0.f);
+    if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+    __syncthreads();  // the previous item's LDS reads (and, first, the tables) are done
+    // the spectrum in natural order (the line stride leaves room for the repeated bin 0)
+    static_assert(C::LSTRIDE > N, "room for bin N");
+    fft_run<S, false, true>(v, p, my, idx, TwLds<S>{wt, wt2}, [&](int n, float2 val) {
+      my[n] = val;
+      if (n == 0) my[N] = val;
+    });
+    __syncthreads();
+    const int kxs = it.kx < a.Mx / 2 ? it.kx : it.kx - a.Mx;
+    const int kys = it.ky < a.My / 2 ? it.ky : it.ky - a.My;
+    const double ax = a.sxk * kxs, ay = a.syk * kys;
+    const double A = ax * ax + ay * ay;
+    const bool mir = it.has_mirror;
+    float2* o1 = outp + (long long)it.ky * a.out_row + (long long)it.kx * a.nt;
+    float2* o2 = mir ? outp + (long long)it.ky2 * a.out_row + (long long)it.kx2 * a.nt : o1;
+#pragma unroll
+    for (int i = 0; i < HALF / P; ++i) {
+      const int kz = p + i * P;
+      float2 xa, xb;
+      stolt_pair_nat(kz, HALF, N, A, a.norm, my, xa, xb);
+      o1[kz] = xa;
+      o2[kz] = mir ? xb : xa;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // mixture of experts (Section 4.4): RSD phasors from the shared spatial spectrum
 // ---------------------------------------------------------------------------
@@ -576,6 +652,14 @@ static hipError_t launch_pair_n(const FkPairArgs& a, const float2* tw, hipStream
   // padded volume, four-byte storage (FP32 keeps its guarded loads: the folded form
   // raised its registers from 157 to 173 and its occupancy from 3 to 2)
   const bool half = SP != SP_F32 && 2 * a.nt == N;
+  if constexpr (SP == SP_F32 && FftShape<N, E>::NSTAGE == 3) {
+    if (a.tscale_in == 0.f && 2 * a.nt == N) {
+      const long long res = resident_blocks<fk_column_pair_stream<N, E>>(C::THREADS);
+      const long long nb = res > 0 && res < groups ? res : groups;
+      hipLaunchKernelGGL((fk_column_pair_stream<N, E>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, a, tw);
+      return hipGetLastError();
+    }
+  }
   if (SP == SP_F32 && a.tscale_in != 0.f)
     hipLaunchKernelGGL((fk_column_pair<N, E, SP_F32, true>), grid, dim3(C::THREADS), 0, s, a, tw);
   else if (a.tscale_in != 0.f)
