@@ -19,6 +19,6 @@ Modules
   merge    -- coherence-weighted temporal merging (Section 4.4, Eq. 8-9)
   metrics  -- error measures (relative L2, PSNR, argmax distance)
 
-Every function states the passage it follows.  Readings of silent or garbled
-passages are listed in the design doc.
+Every function states the passage it follows, and each module states the
+readings it takes where the paper is silent or garbled.
 """

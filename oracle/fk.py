@@ -4,7 +4,7 @@ Follows the f-k pipeline as the paper states it: Section 3.1 (Eq. 1-2: Stolt
 interpolation migrates the wall measurement to t = 0, the volume is |Psi|^2),
 Section 4.2 (scaling fused with zero padding, 3D FFT, on-the-fly Stolt with
 the |fz|/sqrt Jacobian, active half only, inverse 3D FFT) and Algorithms 1-2 of
-the supplementary material.  Readings (the design doc lists them):
+the supplementary material.  Readings taken where the paper is silent:
   * scaling by the normalised time index t/(nt-1), no square root;
   * the fftshift/ifftshift pair of Algorithm 1 is read as signed-frequency
     indexing, with no data movement;

@@ -14,7 +14,7 @@ sqrt(|x|^2 + d^2) + sigma_t d + Delta)) is also given twice, as a direct
 spatial sum and as a dense-kernel FFT convolution (Algorithm 3's operator);
 they pin the radial form.  J0 comes from scipy.special.j0.
 
-Readings (the design doc lists them): kappa_f = 2 pi k_f / (nt c dt); forward DFT
+Readings taken where the paper is silent: kappa_f = 2 pi k_f / (nt c dt); forward DFT
 exp(-i), kernel exp(+i); Delta = 0; output |I|; the amplitude falloff is
 dropped as the paper does; ceilings of quantities that are integers in exact
 arithmetic use a 1e-9 relative tolerance; a stored radial sample is zero when
