@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
   NLOS_OK = 0,
   NLOS_ERR_INVALID_ARG = 1,   /* null pointer, non-positive size, bad enum, value out of range */
-  NLOS_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  NLOS_ERR_UNSUPPORTED = 2,   /* valid request outside what the library implements */
   NLOS_ERR_OUT_OF_MEMORY = 3, /* device allocation failed, or workspace too small */
   NLOS_ERR_DEVICE = 4,        /* HIP runtime or launch failure */
   NLOS_ERR_INTERNAL = 5
