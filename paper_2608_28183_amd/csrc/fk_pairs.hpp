@@ -14,20 +14,23 @@ struct PairItem {
   bool has_mirror;
 };
 
-__device__ __forceinline__ PairItem pair_item(long long w, int Mx, int My) {
+// The work counts stay below 2^24 (Mx, My <= 4096): 32-bit unsigned arithmetic, not the
+// much longer 64-bit division.
+__device__ __forceinline__ PairItem pair_item(long long w64, int Mx, int My) {
   PairItem it;
-  const long long nmain = (long long)(Mx / 2 - 1) * My;
+  const unsigned w = (unsigned)w64, my = (unsigned)My;
+  const unsigned nmain = (unsigned)(Mx / 2 - 1) * my;
   if (w < nmain) {
-    it.kx = 1 + int(w / My);
-    it.ky = int(w % My);
+    it.kx = 1 + int(w / my);
+    it.ky = int(w % my);
     it.kx2 = Mx - it.kx;
     it.ky2 = it.ky == 0 ? 0 : My - it.ky;
     it.has_mirror = true;
   } else {
-    const int half = My / 2 + 1;
-    const int w2 = int(w - nmain);
+    const unsigned half = my / 2 + 1;
+    const unsigned w2 = w - nmain;
     it.kx = (w2 < half) ? 0 : Mx / 2;
-    it.ky = w2 % half;
+    it.ky = int(w2 % half);
     it.kx2 = it.kx;
     it.ky2 = it.ky == 0 ? 0 : My - it.ky;
     it.has_mirror = (it.ky != 0) && (it.ky != My / 2);
