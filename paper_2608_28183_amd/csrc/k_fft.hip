@@ -214,27 +214,21 @@ __global__ __launch_bounds__((ContigCfg<N, ContigTune<N>::E>::THREADS)) void con
   const bool lineok = line < a.nlines;
   float2 v[E];
   if constexpr (LD == CL_REAL || LD == CL_REAL_PAIR) {
+    // real lines: raw loads first, branch-free (a missing line reads a present one and is
+    // zeroed after), so that all of the thread's loads are in flight together
+    static_assert(!HALF, "real lines are not zero-padded here");
     const bool oddok = LD == CL_REAL_PAIR && 2 * line + 1 < a.nreal;  // the pair's second line
-    static_for<E / S::R0>([&](auto b_) {
-      static_for<S::R0>([&](auto r_) {
-        constexpr int b = decltype(b_)::value, r = decltype(r_)::value;
-        const int n = stage_in_index<N, S::R0, E>(p, b, r);
-        float2 x = make_float2(0.f, 0.f);
-        constexpr bool ZERO = HALF && (b * (N / E) + r * (N / S::R0) >= N / 2);  // n >= N/2 for every p
-        if (!ZERO && lineok && n < (HALF ? N / 2 : a.n_in)) {
-          if constexpr (LD == CL_REAL) {
-            x.x = static_cast<const float*>(a.in)[line * a.in_line + n];
-          } else if constexpr (LD == CL_REAL_PAIR) {
-            const float* f = static_cast<const float*>(a.in);
-            x.x = f[2 * line * a.in_line + n];
-            if (oddok) x.y = f[(2 * line + 1) * a.in_line + n];
-          } else {
-            x = static_cast<const float2*>(a.in)[line * a.in_line + n];
-          }
-        }
-        v[b * S::R0 + r] = x;
-      });
-    });
+    const float* f = static_cast<const float*>(a.in);
+    const long long ra = lineok ? (LD == CL_REAL_PAIR ? 2 * line : line) : 0;
+    const float* pa = f + ra * a.in_line;
+    float xa[E], xb[E];
+    load_first_stage<S>(xa, p, a.n_in, lineok, 0.f, [&](int n) { return pa[n]; });
+    if constexpr (LD == CL_REAL_PAIR) {
+      const float* pb = f + (oddok ? 2 * line + 1 : ra) * a.in_line;
+      load_first_stage<S>(xb, p, a.n_in, oddok, 0.f, [&](int n) { return pb[n]; });
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = make_float2(xa[j], LD == CL_REAL_PAIR ? xb[j] : 0.f);
   } else {
     // complex lines: raw loads first, branch-free (a line past the end reads line 0 and
     // is zeroed), conversion of four-byte storage after

@@ -38,6 +38,7 @@ CASES = [
     (20, 18, 96, 1, 16),    # unpadded 20 x 18, t 96
     (14, 11, 154, 2, 6),    # 28 x 22, t 154 = 2 x 7 x 11
     (13, 16, 104, 2, 5),    # 26 x 32, t 104 = 8 x 13
+    (13, 11, 128, 2, 6),    # 26 x 22, t 128: an odd pixel count (the last real pair is one line)
 ]
 
 
